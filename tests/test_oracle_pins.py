@@ -1,0 +1,322 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test fixes a part of the oracle by an independent route: an explicit
+O(N^2) DFT, a plane-wave eigenfunction, the closed-form Fourier series of a
+product of periodised Gaussians, the free-space limit, invariances of the
+exchange operator (Eq. (1) is invariant under rotations of the occupied
+space), and the algebra of the ACE construction.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ace_oracle as O
+from paper_2110_07670_amd import synth
+
+ALPHA = 0.25
+
+
+def _ortho(lengths):
+    return np.diag(np.asarray(lengths, dtype=np.float64))
+
+
+# ----------------------------------------------------------------------- P1
+# Explicit DFT matrix, centred integer frequencies and reciprocal lengths
+# written out here independently of the oracle's helpers.
+
+def _brute_dft(shape):
+    idx = np.indices(shape).reshape(3, -1).T.astype(np.float64)
+    phase = np.zeros((idx.shape[0], idx.shape[0]))
+    for a in range(3):
+        phase += np.outer(idx[:, a], idx[:, a]) / shape[a]
+    return np.exp(-2j * math.pi * phase)
+
+
+def _brute_kernel(shape, lengths):
+    idx = np.indices(shape).reshape(3, -1).T
+    g2 = np.zeros(idx.shape[0])
+    for a in range(3):
+        n = shape[a]
+        m = np.where(idx[:, a] <= n // 2, idx[:, a], idx[:, a] - n)
+        g2 += (2.0 * math.pi * m / lengths[a]) ** 2
+    K = np.zeros_like(g2)
+    K[g2 > 0] = 4.0 * math.pi / g2[g2 > 0]
+    return K
+
+
+def _brute_potential(rho, lengths, F=None):
+    shape = rho.shape
+    N = rho.size
+    F = _brute_dft(shape) if F is None else F
+    K = _brute_kernel(shape, lengths)
+    rh = F @ rho.ravel()
+    v = (F.conj().T @ (K * rh)) / N
+    return v.reshape(shape)
+
+
+@pytest.mark.parametrize("n", [6, 8, 10, 12, 15])
+def test_p1_pair_potential_matches_explicit_dft(n):
+    lengths = (7.0, 8.0, 9.5)
+    shape = (n, n, n)
+    rng = np.random.default_rng(100 + n)
+    rho = rng.standard_normal(shape)
+    v_brute = _brute_potential(rho, lengths)
+    assert np.abs(v_brute.imag).max() < 1e-12 * np.abs(v_brute.real).max()
+    K = O.coulomb_kernel(shape, _ortho(lengths))
+    v = O.pair_potential(rho, K)
+    assert O.rel_err(v, v_brute.real) < 1e-12
+    # (ij|ji) by Parseval against dV sum rho v from the explicit route
+    omega = float(np.prod(lengths))
+    c_brute = omega / rho.size * float(np.sum(rho * v_brute.real))
+    c = O.pair_coulomb(rho, K, omega)
+    assert abs(c - c_brute) < 1e-12 * abs(c_brute)
+
+
+def test_p1_W_matches_explicit_dft_ordered_sum():
+    n, lengths = 8, (6.0, 7.0, 8.0)
+    shape = (n, n, n)
+    rng = np.random.default_rng(7)
+    phi = rng.standard_normal((3,) + shape)
+    F = _brute_dft(shape)
+    W_ref = np.zeros_like(phi)
+    for i in range(3):
+        for j in range(3):
+            v = _brute_potential(phi[i] * phi[j], lengths, F).real
+            W_ref[i] -= ALPHA * v * phi[j]
+    W = O.apply_vx(phi, _ortho(lengths), ALPHA)
+    assert O.rel_err(W, W_ref) < 1e-12
+
+
+# ----------------------------------------------------------------------- P2
+
+def test_p2_plane_wave_is_an_eigenfunction():
+    n, lengths = 12, (9.0, 10.0, 11.0)
+    m0 = (1, -2, 3)
+    p = np.indices((n, n, n)).astype(np.float64)
+    arg = sum(2 * math.pi * m0[a] * p[a] / n for a in range(3))
+    rho = np.cos(arg)
+    g2 = sum((2 * math.pi * m0[a] / lengths[a]) ** 2 for a in range(3))
+    K = O.coulomb_kernel((n, n, n), _ortho(lengths))
+    v = O.pair_potential(rho, K)
+    assert np.abs(v - 4 * math.pi / g2 * rho).max() < 1e-13 * 4 * math.pi / g2
+    # a constant density has no potential (K(0) = 0)
+    assert np.abs(O.pair_potential(np.ones((n, n, n)), K)).max() < 1e-15
+
+
+# ----------------------------------------------------------------------- P3
+
+def _analytic_pair_coulomb(A, sa, B, sb, L, n, alias=2, shifts=2):
+    """(ab|ba) on the grid from the closed-form Fourier series of phi_a phi_b.
+
+    phi_a = sum_T exp(-|r - A - T|^2 / (2 sa^2)) (unnormalised, periodised).
+    The product is the periodisation of sum_S h_S with h_S a Gaussian of
+    variance s^2 = sa^2 sb^2 / (sa^2 + sb^2) centred at
+    P_S = (sb^2 A + sa^2 (B + S)) / (sa^2 + sb^2) and weight
+    exp(-|A - B - S|^2 / (2 (sa^2 + sb^2))).  Its cell Fourier coefficient is
+    c(G) = (1/Omega) sum_S w_S (2 pi s^2)^{3/2} exp(-s^2 G^2 / 2) exp(-i G.P_S),
+    and the DFT of grid samples is N sum_q c(G + n q 2pi/L) (aliasing).
+    """
+    A, B = np.asarray(A, float), np.asarray(B, float)
+    omega = L ** 3
+    N = n ** 3
+    s2 = sa * sa * sb * sb / (sa * sa + sb * sb)
+    t = sa * sa + sb * sb
+    m = np.arange(n)
+    m = np.where(m <= n // 2, m, m - n)
+    M1, M2, M3 = np.meshgrid(m, m, m, indexing="ij")
+    rho_hat = np.zeros(M1.shape, dtype=np.complex128)
+    rng_s = range(-shifts, shifts + 1)
+    for q1 in range(-alias, alias + 1):
+        for q2 in range(-alias, alias + 1):
+            for q3 in range(-alias, alias + 1):
+                G = [2 * math.pi * (M1 + n * q1) / L, 2 * math.pi * (M2 + n * q2) / L,
+                     2 * math.pi * (M3 + n * q3) / L]
+                G2 = G[0] ** 2 + G[1] ** 2 + G[2] ** 2
+                env = (2 * math.pi * s2) ** 1.5 * np.exp(-s2 * G2 / 2.0)
+                if env.max() < 1e-40:
+                    continue
+                phase_sum = np.zeros(M1.shape, dtype=np.complex128)
+                for S1 in rng_s:
+                    for S2 in rng_s:
+                        for S3 in rng_s:
+                            S = np.array([S1, S2, S3], float) * L
+                            d = A - B - S
+                            w = math.exp(-float(d @ d) / (2 * t))
+                            if w < 1e-40:
+                                continue
+                            P = (sb * sb * A + sa * sa * (B + S)) / t
+                            phase_sum += w * np.exp(-1j * (G[0] * P[0] + G[1] * P[1] + G[2] * P[2]))
+                rho_hat += N / omega * env * phase_sum
+    g2 = (2 * math.pi / L) ** 2 * (M1 ** 2 + M2 ** 2 + M3 ** 2)
+    K = np.zeros(g2.shape)
+    K[g2 > 0] = 4 * math.pi / g2[g2 > 0]
+    return omega / N ** 2 * float(np.sum(K * np.abs(rho_hat) ** 2)), rho_hat
+
+
+@pytest.mark.parametrize("case", ["self", "distinct"])
+def test_p3_periodic_gaussian_pair_closed_form(case):
+    L, n = 10.0, 24
+    A, sa = (2.1, 3.3, 7.9), 1.0
+    if case == "self":
+        B, sb = A, sa
+    else:
+        B, sb = (8.4, 1.2, 4.0), 1.2
+    phi_a = synth.gaussian_on_grid(n, L, A, sa)
+    phi_b = synth.gaussian_on_grid(n, L, B, sb)
+    K = O.coulomb_kernel((n, n, n), _ortho((L, L, L)))
+    c_oracle = O.pair_coulomb(phi_a * phi_b, K, L ** 3)
+    c_exact, rho_hat = _analytic_pair_coulomb(A, sa, B, sb, L, n)
+    assert abs(c_oracle - c_exact) < 1e-13 * abs(c_exact)
+    # the same number through the real-space route dV sum rho v
+    v = O.pair_potential(phi_a * phi_b, K)
+    c_real = (L ** 3 / n ** 3) * float(np.sum(phi_a * phi_b * v))
+    assert abs(c_real - c_exact) < 1e-13 * abs(c_exact)
+
+
+# ----------------------------------------------------------------------- P4
+
+def test_p4_free_space_limit_with_madelung_term():
+    """(aa|aa) of a normalised Gaussian density tends to 1/(s sqrt(pi)).
+
+    With K(0) = 0 the periodic value sits below it by the simple-cubic
+    Madelung term 2.837297/L; what is left shrinks like 1/L^3.
+    """
+    sigma = 1.0
+    s = sigma / math.sqrt(2.0)
+    free = 1.0 / (s * math.sqrt(math.pi))
+    resid = []
+    for L, n in [(12.0, 40), (24.0, 80)]:
+        phi = synth.gaussian_on_grid(n, L, (L / 2, L / 2, L / 2), sigma)
+        phi /= math.sqrt((L / n) ** 3 * float(np.sum(phi * phi)))
+        K = O.coulomb_kernel((n, n, n), _ortho((L, L, L)))
+        c = O.pair_coulomb(phi * phi, K, L ** 3)
+        raw = abs(c - free)
+        corrected = abs(c - (free - 2.837297 / L))
+        assert corrected < 0.05 * raw
+        resid.append(corrected)
+    assert resid[1] < resid[0] / 4.0
+
+
+# ----------------------------------------------------------------------- P5-P10
+
+@pytest.fixture(scope="module")
+def small():
+    spec = synth.small_spec(n=16, n_orb=5, L=8.0, seed=21)
+    sysm = synth.build_system(spec)
+    out = O.ace_build(sysm.phi, spec.cell, ALPHA)
+    return spec, sysm, out
+
+
+def test_generator_orthonormal(small):
+    spec, sysm, out = small
+    assert O.orthonormality_defect(sysm.phi, sysm.dV) < 1e-13
+
+
+def test_p5_unitary_invariance(small):
+    spec, sysm, out = small
+    Q = synth.random_orthogonal(spec.n_orb, 5)
+    k = spec.n_orb
+    phi2 = (Q @ sysm.phi.reshape(k, -1)).reshape(sysm.phi.shape)
+    out2 = O.ace_build(phi2, spec.cell, ALPHA)
+    W_rot = (Q @ out["W"].reshape(k, -1)).reshape(out["W"].shape)
+    assert O.rel_err(out2["W"], W_rot) < 1e-12
+    assert O.rel_err(out2["M"], Q @ out["M"] @ Q.T) < 1e-12
+    assert abs(out2["ex"] - out["ex"]) < 1e-12 * abs(out["ex"])
+
+
+def test_p6_pair_halving_equals_all_ordered_pairs(small):
+    spec, sysm, out = small
+    W_all = O.apply_vx(sysm.phi, spec.cell, ALPHA, all_ordered=True)
+    assert O.rel_err(out["W"], W_all) < 1e-13
+    M = out["M"]
+    assert np.abs(M - M.T).max() < 1e-13 * np.abs(M).max()
+    assert np.linalg.eigvalsh(M).max() < 0.0
+
+
+def test_p7_ace_exact_on_occupied_space(small):
+    spec, sysm, out = small
+    back = O.ace_apply(out["xi"], sysm.phi, out["dV"])
+    assert O.rel_err(back, out["W"]) < 1e-12
+    # and dV xi^T Phi = -L^T
+    k = spec.n_orb
+    C = out["dV"] * out["xi"].reshape(k, -1) @ sysm.phi.reshape(k, -1).T
+    assert np.abs(C + out["L"].T).max() < 1e-12 * np.abs(out["L"]).max()
+
+
+def test_p8_trace_is_minus_frobenius_of_cholesky(small):
+    spec, sysm, out = small
+    assert abs(out["ex"] + float(np.sum(out["L"] ** 2))) < 1e-13 * abs(out["ex"])
+
+
+def test_p9_trace_equals_parseval_and_packing(small):
+    spec, sysm, out = small
+    e_pars = O.exchange_energy_parseval(sysm.phi, spec.cell, ALPHA)
+    assert abs(e_pars - out["ex"]) < 1e-13 * abs(out["ex"])
+    # two real pairs share one complex transform exactly (K is real and even)
+    K = O.coulomb_kernel(sysm.phi.shape[1:], spec.cell)
+    ra = sysm.phi[0] * sysm.phi[1]
+    rb = sysm.phi[2] * sysm.phi[2]
+    import scipy.fft as sfft
+    z = sfft.ifftn(K * sfft.fftn(ra + 1j * rb))
+    assert O.rel_err(z.real, O.pair_potential(ra, K)) < 1e-13
+    assert O.rel_err(z.imag, O.pair_potential(rb, K)) < 1e-13
+
+
+def test_p10_single_orbital_is_minus_half_hartree():
+    """One doubly occupied orbital: E_X^HF = -(11|11) = -E_H[2 phi^2] / 2."""
+    spec = synth.small_spec(n=20, n_orb=1, L=9.0, seed=3)
+    sysm = synth.build_system(spec)
+    out = O.ace_build(sysm.phi, spec.cell, 1.0)
+    K = O.coulomb_kernel(sysm.phi.shape[1:], spec.cell)
+    rho = 2.0 * sysm.phi[0] ** 2
+    vh = O.pair_potential(rho, K)
+    e_h = 0.5 * sysm.dV * float(np.sum(rho * vh))
+    assert abs(out["ex"] + 0.5 * e_h) < 1e-13 * e_h
+
+
+def test_p10_alpha_linear_roll_and_permutation(small):
+    spec, sysm, out = small
+    out2 = O.ace_build(sysm.phi, spec.cell, 2 * ALPHA)
+    assert O.rel_err(out2["W"], 2 * out["W"]) < 1e-14
+    assert abs(out2["ex"] - 2 * out["ex"]) < 1e-13 * abs(out["ex"])
+    rolled = np.roll(sysm.phi, shift=(3, -5, 2), axis=(1, 2, 3))
+    out3 = O.ace_build(rolled, spec.cell, ALPHA)
+    assert O.rel_err(out3["M"], out["M"]) < 1e-12
+    assert O.rel_err(out3["W"], np.roll(out["W"], (3, -5, 2), axis=(1, 2, 3))) < 1e-12
+    perm = np.array([3, 0, 4, 1, 2])
+    out4 = O.ace_build(sysm.phi[perm], spec.cell, ALPHA)
+    assert O.rel_err(out4["M"], out["M"][np.ix_(perm, perm)]) < 1e-12
+
+
+def test_singular_M_raises():
+    spec = synth.small_spec(n=12, n_orb=3, L=8.0, seed=4)
+    sysm = synth.build_system(spec)
+    phi = sysm.phi.copy()
+    phi[2] = phi[1]
+    with pytest.raises(O.OracleError):
+        O.ace_build(phi, spec.cell, ALPHA)
+
+
+def test_pair_mask_skips_pairs_and_shards_sum(small):
+    """Disjoint masks add up to the all-pairs W (the group-sum of the paper's CP groups)."""
+    spec, sysm, out = small
+    k = spec.n_orb
+    iu = np.argwhere(np.triu(np.ones((k, k), bool)))
+    Ws = np.zeros_like(out["W"])
+    for part in range(3):
+        mask = np.zeros((k, k), bool)
+        for (i, j) in iu[part::3]:
+            mask[i, j] = True
+        Ws += O.apply_vx(sysm.phi, spec.cell, ALPHA, pair_mask=mask)
+    assert O.rel_err(Ws, out["W"]) < 1e-13
+
+
+def test_overlap_screen_matches_direct_integral(small):
+    spec, sysm, out = small
+    mask, S = O.overlap_screen(sysm.phi, sysm.dV, 0.05)
+    i, j = 1, 3
+    direct = sysm.dV * float(np.sum(np.abs(sysm.phi[i] * sysm.phi[j])))
+    assert abs(S[i, j] - direct) < 1e-13
+    assert mask[i, j] == (direct >= 0.05)
+    assert not mask[3, 1]
