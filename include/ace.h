@@ -1,0 +1,151 @@
+/*
+ * ace.h — C-ABI of the MI355X (gfx950) adaptively compressed exchange build.
+ *
+ * The calls follow the statement of the problem in arXiv 2110.07670,
+ * section "HF Exchange Operator" (Eq. (1)-(4)) and section "ACE Operator":
+ *
+ *   ace_build  : W = alpha V_X Phi (Eq. (2)), one periodic Poisson solve per
+ *                orbital pair (Eq. (3), evaluated in reciprocal space),
+ *                M = dV Phi^T W, -M = L L^T, projectors xi = W L^{-T} (the
+ *                paper's P_k), and E_x = tr(M) = alpha E_X^HF (Eq. (4)).
+ *   ace_apply  : V_ACE psi = -xi (dV xi^T psi)  (the ACE application formula).
+ *   exx_energy : E_x from forward transforms only (Parseval form of Eq. (4)),
+ *                optionally the energy of every pair.
+ *
+ * Conventions (the paper leaves them open; these are the library's readings):
+ *   - Gamma point, real orbitals phi_i sampled on an n1 x n2 x n3 grid of an
+ *     orthorhombic cell with edges L1, L2, L3 (bohr); Omega = L1 L2 L3,
+ *     N = n1 n2 n3, dV = Omega / N, <f, g> = dV sum_r f(r) g(r).
+ *   - Coulomb kernel K(G) = 4 pi / |G|^2 with K(0) = 0, G = 2 pi m_a / L_a,
+ *     m in numpy FFT order (the Nyquist plane is kept); unnormalised forward
+ *     transform, 1/N on the inverse.
+ *   - W_i = -alpha sum_j v_ij phi_j includes alpha and the minus sign; every
+ *     unordered pair i <= j is solved once (v_ij = v_ji) and updates both
+ *     W_i and W_j.  Closed shell: no factor 1/2 in E_x.
+ *   - L is lower triangular with a positive diagonal; a non-positive leading
+ *     minor of -M is reported through *info (LAPACK style); xi is then left
+ *     untouched.
+ *
+ * Layout: phi, W, xi, psi, out are orbital-major [k][n1][n2][n3] float64 in C
+ * order (z fastest, each orbital contiguous).  M is [n_orb][n_orb] row-major.
+ * ex and info are single device values.  pair_mask and pair_e are described
+ * at their calls.
+ *
+ * Ownership: every array is caller-owned device memory, except pair_mask
+ * (host memory).  The library never allocates device memory and never frees
+ * caller memory; each call copies its small tables (twiddles, pair schedule)
+ * into the caller's workspace, stream-ordered.  A plan is immutable host data
+ * and may be shared by several streams if each stream has its own workspace.
+ * Calls that overlap on one workspace race.
+ *
+ * Errors: every argument is validated on the host before any device work; the
+ * return value is an ace_status.  Calls are asynchronous on `stream` (a
+ * hipStream_t; NULL is the default stream): read ex / info after
+ * synchronising the stream.
+ */
+#ifndef ACE_H_
+#define ACE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ace_plan ace_plan;
+
+enum ace_precision {
+  ACE_FP64 = 0, /* all stages in FP64 */
+  ACE_FP32 = 1  /* pair densities, transforms and Coulomb multiply in FP32;
+                   W accumulation, M, Cholesky, xi and E_x stay in FP64 */
+};
+
+enum ace_status {
+  ACE_OK = 0,
+  ACE_ERR_ARG = 1,       /* null pointer, bad count or cell, aliasing outputs */
+  ACE_ERR_SIZE = 2,      /* grid not supported (see ace_plan_create) or n_orb too large */
+  ACE_ERR_WORKSPACE = 3, /* workspace smaller than the call needs */
+  ACE_ERR_HIP = 4,       /* a HIP launch or runtime call failed: see ace_last_hip_error() */
+  ACE_ERR_NODEV = 5      /* no HIP device is visible */
+};
+
+typedef struct {
+  int n[3];        /* grid points per axis; currently n1 = n2 = n3 and n in
+                      {16,24,32,40,48,64,80,96,120,128,144,160,192} (factors 2, 3, 5) */
+  double cell[3];  /* orthorhombic edge lengths L1, L2, L3 in bohr, > 0 */
+  int n_orb;       /* occupied orbitals, 1 .. 4096 */
+  int precision;   /* enum ace_precision */
+  double alpha;    /* exact-exchange fraction (0.25 for PBE0) */
+} ace_desc;
+
+/* Create a host-only plan for one grid / cell / orbital count.  Touches no
+ * device.  Returns ACE_ERR_ARG for a null pointer, n_orb < 1, a non-positive
+ * or non-finite cell edge, an unknown precision or a non-finite alpha;
+ * ACE_ERR_SIZE for a grid outside the supported set or n_orb > 4096.  On
+ * success *plan owns host memory released by ace_plan_destroy. */
+int ace_plan_create(ace_plan **plan, const ace_desc *desc);
+void ace_plan_destroy(ace_plan *plan);
+
+/* Device workspace bytes that ace_build and exx_energy need (0 on a null plan). */
+size_t ace_workspace_bytes(const ace_plan *plan);
+/* Device workspace bytes that ace_apply needs for n_vec vectors. */
+size_t ace_apply_workspace_bytes(const ace_plan *plan, int n_vec);
+
+/* The ACE build (see the file comment).
+ *   phi       [n_orb][N] input orbitals, orthonormal under dV (not checked)
+ *   pair_mask host [n_orb][n_orb] uint8 or NULL; only the upper triangle
+ *             (i <= j) is read; a zero entry skips pair (i, j) for both W_i
+ *             and W_j (the s-MTACE screening of the paper); NULL = all pairs
+ *   W         [n_orb][N] output, alpha V_X phi
+ *   M         [n_orb][n_orb] output, dV Phi^T W
+ *   xi        [n_orb][N] output projectors; untouched when *info != 0
+ *   ex        device double: tr(M)
+ *   info      device int: 0, or k when the k-th leading minor of -M is not
+ *             positive
+ * phi, W and xi must not overlap. */
+int ace_build(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes, const double *phi,
+              const uint8_t *pair_mask, double *W, double *M, double *xi, double *ex, int *info);
+
+/* out[v] = -sum_k xi_k <xi_k, psi_v>, v < n_vec.  xi [n_orb][N] from ace_build,
+ * psi and out [n_vec][N]; out must not overlap xi or psi. */
+int ace_apply(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes, const double *xi,
+              const double *psi, int n_vec, double *out);
+
+/* E_x = -alpha sum_{i<=j} (2 - delta_ij) (ij|ji) with
+ * (ij|ji) = (Omega / N^2) sum_m K(m) |FFT(phi_i phi_j)(m)|^2.
+ *   pair_mask as in ace_build.
+ *   ex      device double output.
+ *   pair_e  NULL, or device [n_orb][n_orb] double: entry (i, j), i <= j, gets
+ *           that pair's share -alpha (2 - delta_ij) (ij|ji); other entries are
+ *           left untouched.  Requesting pair_e solves one pair per transform
+ *           instead of two. */
+int exx_energy(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes, const double *phi,
+               const uint8_t *pair_mask, double *ex, double *pair_e);
+
+/* Static text for a status code. */
+const char *ace_error_string(int code);
+/* The hipError_t behind the calling thread's last ACE_ERR_HIP (0 if none). */
+int ace_last_hip_error(void);
+
+/* Stage timing.  With profiling on, the calls above record a pair of HIP
+ * events around every launch on their stream; ace_profile_read waits for
+ * them, returns per-stage totals in milliseconds and launch counts, and
+ * clears the record.  Stages: 0 yz-forward, 1 x-Poisson, 2 yz-inverse,
+ * 3 W-accumulate, 4 M product, 5 Cholesky + inverse, 6 xi product,
+ * 7 small kernels and table copies, 8 apply products, 9 x-energy.
+ * out_ms and out_count must hold ACE_N_STAGES entries. */
+#define ACE_N_STAGES 10
+int ace_set_profiling(ace_plan *plan, int on);
+int ace_profile_read(ace_plan *plan, double *out_ms, int *out_count);
+
+/* Launch-shape knobs, for the tuner: orbital block of the pair tiles
+ * (8 or 16) and the packed transforms per forward/inverse launch
+ * (0 = a whole tile).  Changing them changes ace_workspace_bytes. */
+int ace_plan_set_tiling(ace_plan *plan, int block, int chunk);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACE_H_ */

@@ -1,0 +1,223 @@
+"""ctypes binding of include/ace.h (argument marshalling only).
+
+Every step of the ACE build runs in the HIP library; this module only turns
+torch tensors into device pointers and the current torch stream into the
+hipStream_t argument.  It fails loudly when the library is missing: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libacex.so")
+
+ACE_OK, ACE_ERR_ARG, ACE_ERR_SIZE, ACE_ERR_WORKSPACE, ACE_ERR_HIP, ACE_ERR_NODEV = range(6)
+ACE_FP64, ACE_FP32 = 0, 1
+N_STAGES = 10
+STAGE_NAMES = ["yz_fwd", "x_poisson", "yz_inv", "w_accumulate", "m_product", "cholesky_inv",
+               "xi_product", "small", "apply_products", "x_energy"]
+EXPORTS = ["ace_plan_create", "ace_plan_destroy", "ace_workspace_bytes",
+           "ace_apply_workspace_bytes", "ace_build", "ace_apply", "exx_energy",
+           "ace_error_string", "ace_last_hip_error", "ace_set_profiling", "ace_profile_read",
+           "ace_plan_set_tiling"]
+
+
+class AceError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = "%s failed: %s" % (where, _error_string(code))
+        if code == ACE_ERR_HIP:
+            msg += " (hipError %d)" % _LIB.ace_last_hip_error()
+        super().__init__(msg)
+
+
+class AceDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("cell", ctypes.c_double * 3), ("n_orb", ctypes.c_int),
+                ("precision", ctypes.c_int), ("alpha", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libacex.so (built in-tree by build.py); raise if it is absent."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError("libacex.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    vp, sz, i, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
+    lib.ace_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(AceDesc)]
+    lib.ace_plan_create.restype = i
+    lib.ace_plan_destroy.argtypes = [vp]
+    lib.ace_plan_destroy.restype = None
+    lib.ace_workspace_bytes.argtypes = [vp]
+    lib.ace_workspace_bytes.restype = sz
+    lib.ace_apply_workspace_bytes.argtypes = [vp, i]
+    lib.ace_apply_workspace_bytes.restype = sz
+    lib.ace_build.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp, vp, vp, vp]
+    lib.ace_build.restype = i
+    lib.ace_apply.argtypes = [vp, vp, vp, sz, vp, vp, i, vp]
+    lib.ace_apply.restype = i
+    lib.exx_energy.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp]
+    lib.exx_energy.restype = i
+    lib.ace_error_string.argtypes = [i]
+    lib.ace_error_string.restype = ctypes.c_char_p
+    lib.ace_last_hip_error.argtypes = []
+    lib.ace_last_hip_error.restype = i
+    lib.ace_set_profiling.argtypes = [vp, i]
+    lib.ace_set_profiling.restype = i
+    lib.ace_profile_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i)]
+    lib.ace_profile_read.restype = i
+    lib.ace_plan_set_tiling.argtypes = [vp, i, i]
+    lib.ace_plan_set_tiling.restype = i
+    _LIB = lib
+    return lib
+
+
+def _error_string(code: int) -> str:
+    return load().ace_error_string(code).decode()
+
+
+def _check(code: int, where: str):
+    if code != ACE_OK:
+        raise AceError(code, where)
+
+
+def _ptr(t) -> int:
+    """Device (or host) address of a torch tensor, None -> 0."""
+    if t is None:
+        return 0
+    return int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _mask_buffer(mask, n_orb: int):
+    if mask is None:
+        return None, 0
+    m = np.ascontiguousarray(np.asarray(mask).astype(np.uint8))
+    if m.shape != (n_orb, n_orb):
+        raise ValueError("pair_mask must be (%d, %d)" % (n_orb, n_orb))
+    return m, m.ctypes.data
+
+
+class Plan:
+    """A host-only ACE plan (grid, cell, orbital count, precision, alpha)."""
+
+    def __init__(self, n: int, cell: Sequence[float], n_orb: int, precision: str = "fp64",
+                 alpha: float = 0.25, grid: Optional[Sequence[int]] = None):
+        lib = load()
+        d = AceDesc()
+        g = list(grid) if grid is not None else [n, n, n]
+        for a in range(3):
+            d.n[a] = int(g[a])
+        cl = list(cell) if np.ndim(cell) == 1 else [float(cell[a][a]) for a in range(3)]
+        for a in range(3):
+            d.cell[a] = float(cl[a])
+        d.n_orb = int(n_orb)
+        d.precision = {"fp64": ACE_FP64, "fp32": ACE_FP32}[precision] if isinstance(precision, str) else int(precision)
+        d.alpha = float(alpha)
+        h = ctypes.c_void_p()
+        _check(lib.ace_plan_create(ctypes.byref(h), ctypes.byref(d)), "ace_plan_create")
+        self._h = h
+        self.n, self.cell, self.n_orb, self.alpha = g[0], cl, int(n_orb), float(alpha)
+        self.precision = d.precision
+        self.npts = g[0] * g[1] * g[2]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _LIB is not None:
+            _LIB.ace_plan_destroy(self._h)
+            self._h = None
+
+    def workspace_bytes(self) -> int:
+        return int(load().ace_workspace_bytes(self._h))
+
+    def apply_workspace_bytes(self, n_vec: int) -> int:
+        return int(load().ace_apply_workspace_bytes(self._h, int(n_vec)))
+
+    def set_tiling(self, block: int, chunk: int = 0):
+        _check(load().ace_plan_set_tiling(self._h, int(block), int(chunk)), "ace_plan_set_tiling")
+
+    def set_profiling(self, on: bool):
+        _check(load().ace_set_profiling(self._h, 1 if on else 0), "ace_set_profiling")
+
+    def profile_read(self):
+        ms = (ctypes.c_double * N_STAGES)()
+        cnt = (ctypes.c_int * N_STAGES)()
+        _check(load().ace_profile_read(self._h, ms, cnt), "ace_profile_read")
+        return {STAGE_NAMES[i]: (ms[i], cnt[i]) for i in range(N_STAGES)}
+
+
+def workspace(nbytes: int, device="cuda"):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def build_into(plan: Plan, phi, W, M, xi, ex, info, ws, pair_mask=None, stream=None):
+    """ace_build on caller-provided torch tensors (no allocation)."""
+    m, mptr = _mask_buffer(pair_mask, plan.n_orb)
+    rc = load().ace_build(plan.handle, _stream(stream), _ptr(ws), ws.numel() * ws.element_size(),
+                          _ptr(phi), mptr or None, _ptr(W), _ptr(M), _ptr(xi), _ptr(ex), _ptr(info))
+    _check(rc, "ace_build")
+
+
+def ace_build(plan: Plan, phi, pair_mask=None, ws=None, stream=None):
+    """W, M, xi, ex, info as torch tensors on phi's device."""
+    import torch
+    dev = phi.device
+    k = plan.n_orb
+    W = torch.empty_like(phi)
+    xi = torch.empty_like(phi)
+    M = torch.empty((k, k), dtype=torch.float64, device=dev)
+    ex = torch.zeros((1,), dtype=torch.float64, device=dev)
+    info = torch.zeros((1,), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(plan.workspace_bytes(), dev)
+    build_into(plan, phi, W, M, xi, ex, info, ws, pair_mask, stream)
+    return {"W": W, "M": M, "xi": xi, "ex": ex, "info": info}
+
+
+def apply_into(plan: Plan, xi, psi, out, ws, stream=None):
+    n_vec = int(psi.shape[0])
+    rc = load().ace_apply(plan.handle, _stream(stream), _ptr(ws), ws.numel() * ws.element_size(),
+                          _ptr(xi), _ptr(psi), n_vec, _ptr(out))
+    _check(rc, "ace_apply")
+
+
+def ace_apply(plan: Plan, xi, psi, ws=None, stream=None):
+    import torch
+    out = torch.empty_like(psi)
+    if ws is None:
+        ws = workspace(plan.apply_workspace_bytes(int(psi.shape[0])), psi.device)
+    apply_into(plan, xi, psi, out, ws, stream)
+    return out
+
+
+def exx_energy(plan: Plan, phi, pair_mask=None, pair_energies: bool = False, ws=None, stream=None):
+    """(ex tensor[1], pair_e tensor[n_orb, n_orb] or None)."""
+    import torch
+    dev = phi.device
+    ex = torch.zeros((1,), dtype=torch.float64, device=dev)
+    pe = torch.zeros((plan.n_orb, plan.n_orb), dtype=torch.float64, device=dev) if pair_energies else None
+    if ws is None:
+        ws = workspace(plan.workspace_bytes(), dev)
+    m, mptr = _mask_buffer(pair_mask, plan.n_orb)
+    rc = load().exx_energy(plan.handle, _stream(stream), _ptr(ws), ws.numel() * ws.element_size(),
+                           _ptr(phi), mptr or None, _ptr(ex), _ptr(pe))
+    _check(rc, "exx_energy")
+    return ex, pe

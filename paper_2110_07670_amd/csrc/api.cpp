@@ -1,0 +1,602 @@
+// Host runtime behind include/ace.h: plan, argument validation, the pair
+// schedule and the stream-ordered launch sequence.  Every check runs on the
+// host before the first device call, so argument errors are reported
+// without a GPU.
+#include "../../include/ace.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "kernels.h"
+
+using acex::Pack;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+constexpr double kTwoPi = 6.28318530717958647692;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Tile {
+  int i0, j0, bi, bj;
+  bool diag;
+  int pack0, npack;
+};
+
+struct ProfRec {
+  int stage;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct ace_plan {
+  int n;
+  double L[3];
+  int n_orb;
+  int prec;
+  double alpha;
+  int64_t npts;
+  double omega, dV;
+  int block;
+  int chunk;
+  // workspace layout (bytes)
+  size_t off_tab, tab_bytes, off_phi32, off_S, off_part, off_L, off_Linv, off_epart, off_epack,
+      total;
+  size_t s_grid_bytes;  // one complex grid of the bulk type
+  int max_pack_tile;
+  int nsplit;
+  int eparts;
+  std::vector<unsigned char> tw_host;  // n twiddles in the bulk type
+  bool profiling = false;
+  std::mutex prof_mu;
+  std::vector<ProfRec> prof;
+};
+
+namespace {
+
+int64_t n_pairs(int k) { return (int64_t)k * (k + 1) / 2; }
+
+void layout(ace_plan* p) {
+  const int B = p->block;
+  const int nb = (p->n_orb + B - 1) / B;
+  const int64_t ntiles = (int64_t)nb * (nb + 1) / 2;
+  const int64_t npair = n_pairs(p->n_orb);
+  const size_t bulk = p->prec == 0 ? sizeof(double) : sizeof(float);
+  p->s_grid_bytes = align256((size_t)p->npts * 2 * bulk);
+  p->max_pack_tile = (B * B + 1) / 2;
+  p->nsplit = acex::gemm_abt_splits(p->n_orb, p->n_orb, p->npts);
+  p->eparts = acex::energy_parts_per_pack(p->n);
+  size_t off = 0;
+  p->off_tab = off;
+  p->tab_bytes = align256((size_t)npair * sizeof(Pack)) + align256((size_t)ntiles * B * B * 2) +
+                 align256((size_t)p->n * 2 * bulk) + align256((size_t)npair * sizeof(int)) +
+                 align256((size_t)npair * sizeof(double));
+  off += align256(p->tab_bytes);
+  p->off_phi32 = off;
+  if (p->prec == 1) off += align256((size_t)p->n_orb * p->npts * sizeof(float));
+  p->off_S = off;
+  off += p->s_grid_bytes * (size_t)p->max_pack_tile;
+  p->off_part = off;
+  off += align256((size_t)p->nsplit * p->n_orb * p->n_orb * sizeof(double));
+  p->off_L = off;
+  off += align256((size_t)p->n_orb * p->n_orb * sizeof(double));
+  p->off_Linv = off;
+  off += align256((size_t)p->n_orb * p->n_orb * sizeof(double));
+  p->off_epart = off;
+  off += align256((size_t)p->max_pack_tile * p->eparts * sizeof(double));
+  p->off_epack = off;
+  off += align256((size_t)npair * sizeof(double));
+  p->total = off;
+}
+
+void make_twiddles(ace_plan* p) {
+  const int n = p->n;
+  p->tw_host.assign((size_t)n * 2 * (p->prec == 0 ? 8 : 4), 0);
+  for (int k = 0; k < n; ++k) {
+    const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)k / n;
+    const long double c = std::cos(ang), s = std::sin(ang);
+    if (p->prec == 0) {
+      double* t = reinterpret_cast<double*>(p->tw_host.data());
+      t[2 * k] = (double)c;
+      t[2 * k + 1] = (double)s;
+    } else {
+      float* t = reinterpret_cast<float*>(p->tw_host.data());
+      t[2 * k] = (float)c;
+      t[2 * k + 1] = (float)s;
+    }
+  }
+}
+
+bool mask_on(const uint8_t* mask, int n_orb, int i, int j) {
+  return mask == nullptr || mask[(size_t)i * n_orb + j] != 0;
+}
+
+// Pair tiles for ace_build: orbital blocks of B; tile (I, J), I <= J; pairs
+// visited a-major inside a tile and packed two per transform.
+void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& packs,
+                    std::vector<int16_t>& slots, std::vector<Tile>& tiles) {
+  const int B = p->block, k = p->n_orb;
+  const int nb = (k + B - 1) / B;
+  packs.clear();
+  tiles.clear();
+  slots.clear();
+  for (int I = 0; I < nb; ++I) {
+    for (int J = I; J < nb; ++J) {
+      Tile t;
+      t.i0 = I * B;
+      t.j0 = J * B;
+      t.bi = std::min(B, k - t.i0);
+      t.bj = std::min(B, k - t.j0);
+      t.diag = (I == J);
+      t.pack0 = (int)packs.size();
+      std::vector<int16_t> sl((size_t)B * B, int16_t(-1));
+      int half = 0;
+      Pack cur{-1, -1, -1, -1};
+      int local = 0;
+      for (int a = 0; a < t.bi; ++a) {
+        for (int b = t.diag ? a : 0; b < t.bj; ++b) {
+          const int i = t.i0 + a, j = t.j0 + b;
+          if (!mask_on(mask, k, i, j)) continue;
+          if (half == 0) {
+            cur = Pack{i, j, -1, -1};
+            sl[(size_t)a * B + b] = int16_t(2 * local);
+            half = 1;
+          } else {
+            cur.c = i;
+            cur.d = j;
+            sl[(size_t)a * B + b] = int16_t(2 * local + 1);
+            packs.push_back(cur);
+            ++local;
+            half = 0;
+          }
+        }
+      }
+      if (half == 1) {
+        packs.push_back(cur);
+        ++local;
+      }
+      t.npack = local;
+      if (t.npack > 0) {
+        tiles.push_back(t);
+        slots.insert(slots.end(), sl.begin(), sl.end());
+      } else {
+        packs.resize(t.pack0);
+      }
+    }
+  }
+}
+
+// Energy schedule: diagonal pairs packed with diagonal pairs and off-diagonal
+// with off-diagonal (so both halves of a transform share one weight), or one
+// pair per transform when per-pair energies are wanted.
+void build_energy_schedule(const ace_plan* p, const uint8_t* mask, bool single,
+                           std::vector<Pack>& packs, std::vector<double>& weight,
+                           std::vector<int>& code) {
+  const int k = p->n_orb;
+  packs.clear();
+  weight.clear();
+  code.clear();
+  for (int cls = 0; cls < 2; ++cls) {
+    int half = 0;
+    Pack cur{-1, -1, -1, -1};
+    for (int i = 0; i < k; ++i) {
+      for (int j = i; j < k; ++j) {
+        if ((i == j) != (cls == 0)) continue;
+        if (!mask_on(mask, k, i, j)) continue;
+        const double w = -p->alpha * (i == j ? 1.0 : 2.0);
+        if (single) {
+          packs.push_back(Pack{i, j, -1, -1});
+          weight.push_back(w);
+          code.push_back(i * k + j);
+          continue;
+        }
+        if (half == 0) {
+          cur = Pack{i, j, -1, -1};
+          half = 1;
+        } else {
+          cur.c = i;
+          cur.d = j;
+          packs.push_back(cur);
+          weight.push_back(w);
+          code.push_back(-1);
+          half = 0;
+        }
+      }
+    }
+    if (half == 1) {
+      packs.push_back(cur);
+      weight.push_back(-p->alpha * (cls == 0 ? 1.0 : 2.0));
+      code.push_back(-1);
+    }
+  }
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + nb && y < x + na;
+}
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return ACE_ERR_HIP;
+}
+
+int device_present() {
+  int count = 0;
+  const hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return 1;
+}
+
+struct ProfScope {
+  ace_plan* p;
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(const ace_plan* plan, int st, hipStream_t strm)
+      : p(const_cast<ace_plan*>(plan)), stage(st), s(strm) {
+    if (!p->profiling) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      a = b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> g(p->prof_mu);
+    p->prof.push_back(ProfRec{stage, a, b});
+  }
+};
+
+}  // namespace
+
+// ====================================================================== C-ABI
+
+extern "C" {
+
+const char* ace_error_string(int code) {
+  switch (code) {
+    case ACE_OK: return "ok";
+    case ACE_ERR_ARG: return "invalid argument";
+    case ACE_ERR_SIZE: return "unsupported size";
+    case ACE_ERR_WORKSPACE: return "workspace too small";
+    case ACE_ERR_HIP: return "HIP runtime error";
+    case ACE_ERR_NODEV: return "no HIP device";
+    default: return "unknown status";
+  }
+}
+
+int ace_last_hip_error(void) { return g_last_hip; }
+
+int ace_plan_create(ace_plan** plan, const ace_desc* d) {
+  if (!plan || !d) return ACE_ERR_ARG;
+  *plan = nullptr;
+  if (d->n_orb < 1) return ACE_ERR_ARG;
+  for (int a = 0; a < 3; ++a)
+    if (!(d->cell[a] > 0.0) || !std::isfinite(d->cell[a])) return ACE_ERR_ARG;
+  if (d->precision != ACE_FP64 && d->precision != ACE_FP32) return ACE_ERR_ARG;
+  if (!std::isfinite(d->alpha)) return ACE_ERR_ARG;
+  if (d->n[0] != d->n[1] || d->n[1] != d->n[2]) return ACE_ERR_SIZE;
+  if (!acex::supported_n(d->n[0])) return ACE_ERR_SIZE;
+  if (d->n_orb > 4096) return ACE_ERR_SIZE;
+  ace_plan* p = new ace_plan();
+  p->n = d->n[0];
+  for (int a = 0; a < 3; ++a) p->L[a] = d->cell[a];
+  p->n_orb = d->n_orb;
+  p->prec = d->precision;
+  p->alpha = d->alpha;
+  p->npts = (int64_t)p->n * p->n * p->n;
+  p->omega = d->cell[0] * d->cell[1] * d->cell[2];
+  p->dV = p->omega / (double)p->npts;
+  p->block = 16;
+  p->chunk = 0;
+  layout(p);
+  make_twiddles(p);
+  *plan = p;
+  return ACE_OK;
+}
+
+void ace_plan_destroy(ace_plan* plan) {
+  if (!plan) return;
+  for (auto& r : plan->prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  delete plan;
+}
+
+size_t ace_workspace_bytes(const ace_plan* plan) { return plan ? plan->total : 0; }
+
+size_t ace_apply_workspace_bytes(const ace_plan* plan, int n_vec) {
+  if (!plan || n_vec < 1) return 0;
+  const int ns = acex::gemm_abt_splits(n_vec, plan->n_orb, plan->npts);
+  return align256((size_t)n_vec * plan->n_orb * sizeof(double)) +
+         align256((size_t)ns * n_vec * plan->n_orb * sizeof(double));
+}
+
+int ace_plan_set_tiling(ace_plan* plan, int block, int chunk) {
+  if (!plan) return ACE_ERR_ARG;
+  if (block != 8 && block != 16) return ACE_ERR_ARG;
+  if (chunk < 0) return ACE_ERR_ARG;
+  plan->block = block;
+  plan->chunk = chunk;
+  layout(plan);
+  return ACE_OK;
+}
+
+int ace_set_profiling(ace_plan* plan, int on) {
+  if (!plan) return ACE_ERR_ARG;
+  plan->profiling = on != 0;
+  return ACE_OK;
+}
+
+int ace_profile_read(ace_plan* plan, double* out_ms, int* out_count) {
+  if (!plan || !out_ms || !out_count) return ACE_ERR_ARG;
+  for (int i = 0; i < ACE_N_STAGES; ++i) {
+    out_ms[i] = 0.0;
+    out_count[i] = 0;
+  }
+  std::lock_guard<std::mutex> g(plan->prof_mu);
+  int rc = ACE_OK;
+  for (auto& r : plan->prof) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) rc = hip_fail(e);
+    if (r.stage >= 0 && r.stage < ACE_N_STAGES) {
+      out_ms[r.stage] += ms;
+      out_count[r.stage] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  plan->prof.clear();
+  return rc;
+}
+
+int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const double* phi,
+              const uint8_t* pair_mask, double* W, double* M, double* xi, double* ex, int* info) {
+  if (!p || !ws || !phi || !W || !M || !xi || !ex || !info) return ACE_ERR_ARG;
+  const size_t orb_bytes = (size_t)p->n_orb * p->npts * sizeof(double);
+  if (overlaps(phi, orb_bytes, W, orb_bytes) || overlaps(phi, orb_bytes, xi, orb_bytes) ||
+      overlaps(W, orb_bytes, xi, orb_bytes))
+    return ACE_ERR_ARG;
+  if (ws_bytes < p->total) return ACE_ERR_WORKSPACE;
+  if (!device_present()) return ACE_ERR_NODEV;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  hipError_t e;
+
+  // ---- A0: pair schedule (host) and tables
+  std::vector<Pack> packs;
+  std::vector<int16_t> slots;
+  std::vector<Tile> tiles;
+  build_schedule(p, pair_mask, packs, slots, tiles);
+  const int B = p->block;
+  const size_t bulk = p->prec == 0 ? 8 : 4;
+  const size_t o_packs = 0;
+  const size_t o_slots = o_packs + align256(std::max<size_t>(packs.size(), 1) * sizeof(Pack));
+  const size_t o_tw = o_slots + align256(std::max<size_t>(slots.size(), 1) * 2);
+  const size_t tab_used = o_tw + align256((size_t)p->n * 2 * bulk);
+  if (tab_used > p->tab_bytes) return ACE_ERR_SIZE;
+  std::vector<unsigned char> host(tab_used, 0);
+  if (!packs.empty()) std::memcpy(host.data() + o_packs, packs.data(), packs.size() * sizeof(Pack));
+  if (!slots.empty()) std::memcpy(host.data() + o_slots, slots.data(), slots.size() * 2);
+  std::memcpy(host.data() + o_tw, p->tw_host.data(), p->tw_host.size());
+  {
+    ProfScope ps(p, 7, s);
+    e = hipMemcpyAsync(w + p->off_tab, host.data(), tab_used, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  const Pack* d_packs = reinterpret_cast<const Pack*>(w + p->off_tab + o_packs);
+  const int16_t* d_slots = reinterpret_cast<const int16_t*>(w + p->off_tab + o_slots);
+
+  acex::GridArgs g;
+  g.n = p->n;
+  g.prec = p->prec;
+  g.npts = p->npts;
+  for (int a = 0; a < 3; ++a) g.g2[a] = (kTwoPi / p->L[a]) * (kTwoPi / p->L[a]);
+  g.kscale = 1.0 / (double)p->npts;
+  g.tw = w + p->off_tab + o_tw;
+
+  const void* phi_bulk = phi;
+  {
+    ProfScope ps(p, 7, s);
+    if (p->prec == 1) {
+      e = acex::launch_cast_f64_f32(phi, reinterpret_cast<float*>(w + p->off_phi32),
+                                    (int64_t)p->n_orb * p->npts, s);
+      if (e != hipSuccess) return hip_fail(e);
+      phi_bulk = w + p->off_phi32;
+    }
+    e = acex::launch_fill_f64(W, 0.0, (int64_t)p->n_orb * p->npts, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+
+  // ---- A1-A5: pair densities, Poisson solves, W accumulation, tile by tile
+  void* S = w + p->off_S;
+  for (size_t ti = 0; ti < tiles.size(); ++ti) {
+    const Tile& t = tiles[ti];
+    const int chunk = p->chunk > 0 ? p->chunk : t.npack;
+    for (int c0 = 0; c0 < t.npack; c0 += chunk) {
+      const int cnt = std::min(chunk, t.npack - c0);
+      void* Sc = static_cast<char*>(S) + (size_t)c0 * p->s_grid_bytes;
+      {
+        ProfScope ps(p, 0, s);
+        e = acex::launch_fwd_yz(g, phi_bulk, d_packs + t.pack0 + c0, cnt, Sc, s);
+        if (e != hipSuccess) return hip_fail(e);
+      }
+      {
+        ProfScope ps(p, 1, s);
+        e = acex::launch_poisson_x(g, Sc, cnt, s);
+        if (e != hipSuccess) return hip_fail(e);
+      }
+      {
+        ProfScope ps(p, 2, s);
+        e = acex::launch_inv_yz(g, Sc, cnt, s);
+        if (e != hipSuccess) return hip_fail(e);
+      }
+    }
+    {
+      ProfScope ps(p, 3, s);
+      e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W, d_slots + ti * (size_t)B * B,
+                                  t.i0, t.j0, t.bi, t.bj, p->alpha, p->npts, s);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+  }
+
+  // ---- A6: M = dV Phi^T W
+  double* part = reinterpret_cast<double*>(w + p->off_part);
+  {
+    ProfScope ps(p, 4, s);
+    e = acex::launch_gemm_abt(phi, W, p->n_orb, p->n_orb, p->npts, p->dV, M, part, p->nsplit,
+                              false, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  // ---- A7: -M = L L^T, L^{-1}
+  double* L = reinterpret_cast<double*>(w + p->off_L);
+  double* Linv = reinterpret_cast<double*>(w + p->off_Linv);
+  {
+    ProfScope ps(p, 5, s);
+    e = acex::launch_cholesky_inv(M, p->n_orb, L, Linv, info, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  // ---- A8: xi = W L^{-T}, i.e. xi_k = sum_i Linv[k][i] W_i
+  {
+    ProfScope ps(p, 6, s);
+    e = acex::launch_gemm_ab(Linv, W, p->n_orb, p->n_orb, p->npts, 1.0, xi, info, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  // ---- A10: E_x = tr(M)
+  {
+    ProfScope ps(p, 7, s);
+    e = acex::launch_trace(M, p->n_orb, ex, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return ACE_OK;
+}
+
+int ace_apply(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const double* xi,
+              const double* psi, int n_vec, double* out) {
+  if (!p || !ws || !xi || !psi || !out) return ACE_ERR_ARG;
+  if (n_vec < 1) return ACE_ERR_ARG;
+  const size_t xi_bytes = (size_t)p->n_orb * p->npts * sizeof(double);
+  const size_t v_bytes = (size_t)n_vec * p->npts * sizeof(double);
+  if (overlaps(out, v_bytes, xi, xi_bytes) || overlaps(out, v_bytes, psi, v_bytes))
+    return ACE_ERR_ARG;
+  if (ws_bytes < ace_apply_workspace_bytes(p, n_vec)) return ACE_ERR_WORKSPACE;
+  if (!device_present()) return ACE_ERR_NODEV;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  double* C = reinterpret_cast<double*>(w);
+  double* part = reinterpret_cast<double*>(w + align256((size_t)n_vec * p->n_orb * sizeof(double)));
+  const int ns = acex::gemm_abt_splits(n_vec, p->n_orb, p->npts);
+  ProfScope ps(p, 8, s);
+  // C[v][k] = dV <psi_v, xi_k>
+  hipError_t e = acex::launch_gemm_abt(psi, xi, n_vec, p->n_orb, p->npts, p->dV, C, part, ns,
+                                       false, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e);
+  // out[v] = -sum_k C[v][k] xi_k
+  e = acex::launch_gemm_ab(C, xi, n_vec, p->n_orb, p->npts, -1.0, out, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e);
+  return ACE_OK;
+}
+
+int exx_energy(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const double* phi,
+               const uint8_t* pair_mask, double* ex, double* pair_e) {
+  if (!p || !ws || !phi || !ex) return ACE_ERR_ARG;
+  if (ws_bytes < p->total) return ACE_ERR_WORKSPACE;
+  if (!device_present()) return ACE_ERR_NODEV;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  hipError_t e;
+  std::vector<Pack> packs;
+  std::vector<double> weight;
+  std::vector<int> code;
+  build_energy_schedule(p, pair_mask, pair_e != nullptr, packs, weight, code);
+  const int np = (int)packs.size();
+  const size_t bulk = p->prec == 0 ? 8 : 4;
+  const size_t o_packs = 0;
+  const size_t o_tw = o_packs + align256(std::max<size_t>(np, 1) * sizeof(Pack));
+  const size_t o_w = o_tw + align256((size_t)p->n * 2 * bulk);
+  const size_t o_code = o_w + align256(std::max<size_t>(np, 1) * sizeof(double));
+  const size_t tab_used = o_code + align256(std::max<size_t>(np, 1) * sizeof(int));
+  if (tab_used > p->tab_bytes) return ACE_ERR_SIZE;
+  std::vector<unsigned char> host(tab_used, 0);
+  if (np) {
+    std::memcpy(host.data() + o_packs, packs.data(), (size_t)np * sizeof(Pack));
+    std::memcpy(host.data() + o_w, weight.data(), (size_t)np * sizeof(double));
+    std::memcpy(host.data() + o_code, code.data(), (size_t)np * sizeof(int));
+  }
+  std::memcpy(host.data() + o_tw, p->tw_host.data(), p->tw_host.size());
+  {
+    ProfScope ps(p, 7, s);
+    e = hipMemcpyAsync(w + p->off_tab, host.data(), tab_used, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  const Pack* d_packs = reinterpret_cast<const Pack*>(w + p->off_tab + o_packs);
+  const double* d_w = reinterpret_cast<const double*>(w + p->off_tab + o_w);
+  const int* d_code = reinterpret_cast<const int*>(w + p->off_tab + o_code);
+  acex::GridArgs g;
+  g.n = p->n;
+  g.prec = p->prec;
+  g.npts = p->npts;
+  for (int a = 0; a < 3; ++a) g.g2[a] = (kTwoPi / p->L[a]) * (kTwoPi / p->L[a]);
+  g.kscale = 1.0;
+  g.tw = w + p->off_tab + o_tw;
+  const void* phi_bulk = phi;
+  if (p->prec == 1) {
+    ProfScope ps(p, 7, s);
+    e = acex::launch_cast_f64_f32(phi, reinterpret_cast<float*>(w + p->off_phi32),
+                                  (int64_t)p->n_orb * p->npts, s);
+    if (e != hipSuccess) return hip_fail(e);
+    phi_bulk = w + p->off_phi32;
+  }
+  void* S = w + p->off_S;
+  double* epart = reinterpret_cast<double*>(w + p->off_epart);
+  double* epack = reinterpret_cast<double*>(w + p->off_epack);
+  const double factor = p->omega / ((double)p->npts * (double)p->npts);
+  const int chunk = p->max_pack_tile;
+  for (int c0 = 0; c0 < np; c0 += chunk) {
+    const int cnt = std::min(chunk, np - c0);
+    {
+      ProfScope ps(p, 0, s);
+      e = acex::launch_fwd_yz(g, phi_bulk, d_packs + c0, cnt, S, s);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+    {
+      ProfScope ps(p, 9, s);
+      e = acex::launch_energy_x(g, S, cnt, epart, s);
+      if (e != hipSuccess) return hip_fail(e);
+      e = acex::launch_energy_reduce(epart, cnt, p->eparts, factor, epack + c0, s);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+  }
+  ProfScope ps(p, 7, s);
+  if (np == 0) {
+    e = acex::launch_fill_f64(ex, 0.0, 1, s);
+  } else {
+    e = acex::launch_weighted_sum(epack, d_w, np, ex, s);
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  if (pair_e && np) {
+    e = acex::launch_scatter_pair_energies(epack, d_code, np, p->n_orb, -p->alpha, pair_e, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return ACE_OK;
+}
+
+}  // extern "C"

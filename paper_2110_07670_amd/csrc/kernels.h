@@ -1,0 +1,81 @@
+// Internal launch interface between the host runtime and the gfx950 kernels.
+// Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace acex {
+
+// One packed transform carries two real pairs: rho = phi_a phi_b + i phi_c phi_d.
+// c = d = -1 marks a transform carrying a single pair.
+struct Pack {
+  int a, b, c, d;
+};
+
+struct GridArgs {
+  int n;              // points per axis (cubic grid)
+  int prec;           // 0: FP64 bulk, 1: FP32 bulk
+  int64_t npts;       // n^3
+  double g2[3];       // (2 pi / L_a)^2 per axis
+  double kscale;      // multiplies 4 pi / G^2 (1/N for the Poisson pass, 1 for energy)
+  const void* tw;     // n twiddles w_n^k = exp(-2 pi i k / n), bulk precision
+};
+
+// Does one (y, z) plane of the bulk type fit in a workgroup's LDS?
+bool plane_fits(int n, int prec);
+bool supported_n(int n);
+
+// Forward (y,z) transforms of the pair densities of `npack` packed pairs.
+// phi: FP64 orbitals (prec 0) or FP32 copy (prec 1), orbital-major.
+// S: npack complex grids of the bulk type, written in position order.
+hipError_t launch_fwd_yz(const GridArgs& g, const void* phi, const Pack* packs, int npack,
+                         void* S, hipStream_t s);
+// x transforms with the Coulomb multiply between forward and inverse, in place.
+hipError_t launch_poisson_x(const GridArgs& g, void* S, int npack, hipStream_t s);
+// x forward transform and sum of K |Z|^2 per workgroup into part[npack][parts_per_pack].
+hipError_t launch_energy_x(const GridArgs& g, const void* S, int npack, double* part,
+                           hipStream_t s);
+int energy_parts_per_pack(int n);
+// Inverse (y,z) transforms back to real space, natural order, in place.
+hipError_t launch_inv_yz(const GridArgs& g, void* S, int npack, hipStream_t s);
+
+// W tile update: W_I -= alpha sum_j v_ij phi_j, W_J -= alpha sum_i v_ij phi_i.
+// slots[a*B + b] = 2*pack + half (re/im) of pair (i0+a, j0+b), or -1.
+hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const double* phi,
+                             double* W, const int16_t* slots, int i0, int j0, int bi, int bj,
+                             double alpha, int64_t npts, hipStream_t s);
+
+// Pair energies from the per-workgroup partial sums.
+// e_pack[p] = sum of the parts of pack p (fixed order) * omega / N^2.
+hipError_t launch_energy_reduce(const double* part, int npack, int parts, double factor,
+                                double* e_pack, hipStream_t s);
+
+// Small utility kernels.
+hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s);
+hipError_t launch_cast_f64_f32(const double* in, float* out, int64_t count, hipStream_t s);
+
+// Dense FP64 kernels (MFMA) and the small factorisation.
+// C[m][n] = scale * sum_k A[m][k] B[n][k] for A (m x K), B (n x K) row-major,
+// split over K into `nsplit` partial products reduced in a fixed order.
+hipError_t launch_gemm_abt(const double* A, const double* B, int m, int n, int64_t K,
+                           double scale, double* C, double* partial, int nsplit,
+                           bool abs_inputs, const int* skip_if_nonzero, hipStream_t s);
+int gemm_abt_splits(int m, int n, int64_t K);
+// Out[m][r] = scale * sum_k A[m][k] B[k][r]; A (m x k) row-major small, B (k x R) row-major.
+hipError_t launch_gemm_ab(const double* A, const double* B, int m, int k, int64_t R,
+                          double scale, double* Out, const int* skip_if_nonzero, hipStream_t s);
+// -M = L L^T (lower), then Linv = L^{-1}; info = 0 or the order of the first
+// non-positive leading minor.  work: n*n doubles.
+hipError_t launch_cholesky_inv(const double* M, int n, double* L, double* Linv, int* info,
+                               hipStream_t s);
+hipError_t launch_trace(const double* M, int n, double* out, hipStream_t s);
+// out = sum_i w[i] e[i] in a fixed order (single workgroup)
+hipError_t launch_weighted_sum(const double* e, const double* w, int count, double* out,
+                               hipStream_t s);
+hipError_t launch_scatter_pair_energies(const double* e_pack, const int* pair_of_pack,
+                                        int npack, int n_orb, double weight_scale,
+                                        double* pair_e, hipStream_t s);
+
+}  // namespace acex

@@ -1,0 +1,709 @@
+// Per-pair periodic Poisson solves on gfx950 (arXiv 2110.07670, Eq. (3) in
+// reciprocal space, accumulated into V_X phi as in Eq. (2)).
+//
+// One packed transform carries two real pair densities,
+// rho = phi_a phi_b + i phi_c phi_d; since the Coulomb kernel K(G) = 4 pi/|G|^2
+// is real and even in G, the real and imaginary parts of IFFT(K FFT(rho)) are
+// exactly the two pair potentials.
+//
+// A 3-D transform is done in three passes over a complex grid S[x][y][z]:
+//   fwd_yz : pair density, then y and z transforms of each x plane held in
+//            LDS (plane kernel), written in "position order";
+//   poisson_x : x transform of z-adjacent pencils, multiply by K/N, inverse
+//            x transform, in place;
+//   inv_yz : inverse y and z transforms of each x plane, natural order.
+// Position order: after the forward four-step transform of length N = N1*N2,
+// position a + N2*b holds frequency b + N1*a; the inverse consumes it, so no
+// reordering pass exists anywhere.  Where a plane does not fit the 160 KiB
+// LDS, the y/z stage is split into a row (z) pass and a column (y) pass.
+#include "fft_core.h"
+#include "kernels.h"
+
+namespace acex {
+
+// ------------------------------------------------------------------ sizes
+
+template <typename T>
+constexpr int cx_bytes() { return int(sizeof(cx<T>)); }
+
+constexpr int kLdsBytes = 163840;
+
+template <typename T, int N>
+constexpr bool plane_ok() {
+  return (long)N * (N + 1) * (long)sizeof(cx<T>) + 64 <= kLdsBytes;
+}
+
+// threads per plane workgroup: a multiple of 64 and of N2
+template <int N>
+constexpr int plane_threads() {
+  switch (N) {
+    case 16: return 64;
+    case 24: return 128;
+    case 32: return 256;
+    case 40: return 320;
+    case 48: return 384;
+    case 64: return 512;
+    case 80: return 640;
+    case 96: return 768;
+    case 120: return 640;
+    case 128: return 1024;
+    case 144: return 576;
+    case 160: return 640;
+    default: return 768;
+  }
+}
+
+// pencils per strided-lines workgroup (consecutive z positions)
+template <int N>
+constexpr int line_chunk() { return (N % 16 == 0) ? 16 : 8; }
+
+template <int N>
+constexpr int line_threads() {
+  constexpr int C = line_chunk<N>();
+  constexpr int N2 = fft_split<N>::N2;
+  constexpr int t = C * N2;
+  return ((t + 63) / 64) * 64;
+}
+
+// rows per row-pass workgroup (fallback)
+constexpr int kRowsPerBlock = 8;
+template <int N>
+constexpr int row_threads() {
+  constexpr int t = kRowsPerBlock * fft_split<N>::N2;
+  int nt = ((t + 63) / 64) * 64;
+  while (nt % fft_split<N>::N2 != 0) nt += 64;
+  return nt;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ T coulomb_k(int kx, int ky, int kz, T g0, T g1, T g2, T kscale) {
+  const int mx = kx <= N / 2 ? kx : kx - N;
+  const int my = ky <= N / 2 ? ky : ky - N;
+  const int mz = kz <= N / 2 ? kz : kz - N;
+  const T G2 = g0 * T(mx * mx) + g1 * T(my * my) + g2 * T(mz * mz);
+  return G2 > T(0) ? (T(4.0 * kPi) * kscale) / G2 : T(0);
+}
+
+// ------------------------------------------------------------------ y/z plane, forward
+// blockIdx -> (x, pack): consecutive block ids go to the 8 XCDs in turn, so
+// the blocks that share x (and hence the same orbital planes) land on the same
+// XCD and reuse its L2.
+__device__ __forceinline__ void plane_block(int n, int npack, int& x, int& p) {
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7;
+  const int q = bid >> 3;
+  const int xh = q / npack;
+  p = q - xh * npack;
+  x = xcd + 8 * xh;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_fwd(
+    const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
+    cx<T>* __restrict__ S, int npack, int64_t npts) {
+  constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
+  constexpr int NT = plane_threads<N>();
+  static_assert(NT % N2 == 0, "threads must be a multiple of N2");
+  __shared__ cx<T> lds[N * P];
+  int x, p;
+  plane_block(N, npack, x, p);
+  const Pack pk = packs[p];
+  const int tid = threadIdx.x;
+  const int t2 = tid % N2;
+  cx<T> w[N1];
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) w[k1] = tw[t2 * k1];
+
+  const int64_t plane = (int64_t)x * N * N;
+  const T* __restrict__ pa = phi + (int64_t)pk.a * npts + plane;
+  const T* __restrict__ pb = phi + (int64_t)pk.b * npts + plane;
+  const bool two = pk.c >= 0;
+  const T* __restrict__ pc = phi + (int64_t)(two ? pk.c : pk.a) * npts + plane;
+  const T* __restrict__ pd = phi + (int64_t)(two ? pk.d : pk.a) * npts + plane;
+
+  // z step 1: tasks (y, t2), t2 fastest (coalesced along z)
+  for (int task = tid; task < N * N2; task += NT) {
+    const int y = task / N2;
+    cx<T> v[N1];
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) {
+      const int off = y * N + t2 + N2 * j1;
+      const T ra = pa[off] * pb[off];
+      const T rb = two ? pc[off] * pd[off] : T(0);
+      v[j1] = {ra, rb};
+    }
+    dft<N1, false>(v);
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], w[k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) lds[y * P + t2 + N2 * k1] = v[k1];
+  }
+  __syncthreads();
+  // z step 2: tasks (y, k1), y fastest
+  for (int task = tid; task < N * N1; task += NT) {
+    const int y = task % N, k1 = task / N;
+    cx<T> v[N2];
+#pragma unroll
+    for (int t = 0; t < N2; ++t) v[t] = lds[y * P + t + N2 * k1];
+    dft<N2, false>(v);
+#pragma unroll
+    for (int t = 0; t < N2; ++t) lds[y * P + t + N2 * k1] = v[t];
+  }
+  __syncthreads();
+  // y step 1: tasks (pz, t2)
+  for (int task = tid; task < N * N2; task += NT) {
+    const int pz = task / N2;
+    cx<T> v[N1];
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) v[j1] = lds[(t2 + N2 * j1) * P + pz];
+    dft<N1, false>(v);
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], w[k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * P + pz] = v[k1];
+  }
+  __syncthreads();
+  // y step 2 -> global: tasks (pz, k1), pz fastest (coalesced)
+  cx<T>* __restrict__ out = S + (int64_t)p * npts + plane;
+  for (int task = tid; task < N * N1; task += NT) {
+    const int pz = task % N, k1 = task / N;
+    cx<T> v[N2];
+#pragma unroll
+    for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * P + pz];
+    dft<N2, false>(v);
+#pragma unroll
+    for (int t = 0; t < N2; ++t) out[(t + N2 * k1) * N + pz] = v[t];
+  }
+}
+
+// ------------------------------------------------------------------ y/z plane, inverse
+template <typename T, int N>
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_inv(
+    cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts) {
+  constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
+  constexpr int NT = plane_threads<N>();
+  __shared__ cx<T> lds[N * P];
+  const int bid = blockIdx.x;
+  const int x = bid % N, p = bid / N;
+  const int tid = threadIdx.x;
+  const int t2 = tid % N2;
+  cx<T> w[N1];
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) w[k1] = tw[t2 * k1];
+  cx<T>* __restrict__ io = S + (int64_t)p * npts + (int64_t)x * N * N;
+
+  // y step 2 inverse: global positions -> LDS, tasks (pz, k1), pz fastest
+  for (int task = tid; task < N * N1; task += NT) {
+    const int pz = task % N, k1 = task / N;
+    cx<T> v[N2];
+#pragma unroll
+    for (int t = 0; t < N2; ++t) v[t] = io[(t + N2 * k1) * N + pz];
+    dft<N2, true>(v);
+#pragma unroll
+    for (int t = 0; t < N2; ++t) lds[(t + N2 * k1) * P + pz] = v[t];
+  }
+  __syncthreads();
+  // y step 1 inverse: tasks (pz, t2)
+  for (int task = tid; task < N * N2; task += NT) {
+    const int pz = task / N2;
+    cx<T> v[N1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[(t2 + N2 * k1) * P + pz], w[k1]);
+    dft<N1, true>(v);
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) lds[(t2 + N2 * j1) * P + pz] = v[j1];
+  }
+  __syncthreads();
+  // z step 2 inverse: tasks (y, k1), y fastest
+  for (int task = tid; task < N * N1; task += NT) {
+    const int y = task % N, k1 = task / N;
+    cx<T> v[N2];
+#pragma unroll
+    for (int t = 0; t < N2; ++t) v[t] = lds[y * P + t + N2 * k1];
+    dft<N2, true>(v);
+#pragma unroll
+    for (int t = 0; t < N2; ++t) lds[y * P + t + N2 * k1] = v[t];
+  }
+  __syncthreads();
+  // z step 1 inverse -> global natural order: tasks (y, t2)
+  for (int task = tid; task < N * N2; task += NT) {
+    const int y = task / N2;
+    cx<T> v[N1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[y * P + t2 + N2 * k1], w[k1]);
+    dft<N1, true>(v);
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) io[y * N + t2 + N2 * j1] = v[j1];
+  }
+}
+
+// ------------------------------------------------------------------ z rows (fallback)
+// Forward: pair density + z transform of kRowsPerBlock consecutive rows,
+// written in position order.
+template <typename T, int N>
+__global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
+    const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
+    cx<T>* __restrict__ S, int npack, int64_t npts) {
+  constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
+  constexpr int NT = row_threads<N>(), R = kRowsPerBlock;
+  __shared__ cx<T> lds[R * P];
+  constexpr int nrb = N * N / R;
+  const int rb = blockIdx.x % nrb, p = blockIdx.x / nrb;
+  const Pack pk = packs[p];
+  const int tid = threadIdx.x, t2 = tid % N2;
+  cx<T> w[N1];
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) w[k1] = tw[t2 * k1];
+  const int64_t row0 = (int64_t)rb * R * N;
+  const T* __restrict__ pa = phi + (int64_t)pk.a * npts + row0;
+  const T* __restrict__ pb = phi + (int64_t)pk.b * npts + row0;
+  const bool two = pk.c >= 0;
+  const T* __restrict__ pc = phi + (int64_t)(two ? pk.c : pk.a) * npts + row0;
+  const T* __restrict__ pd = phi + (int64_t)(two ? pk.d : pk.a) * npts + row0;
+  for (int task = tid; task < R * N2; task += NT) {
+    const int y = task / N2;
+    cx<T> v[N1];
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) {
+      const int off = y * N + t2 + N2 * j1;
+      v[j1] = {pa[off] * pb[off], two ? pc[off] * pd[off] : T(0)};
+    }
+    dft<N1, false>(v);
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], w[k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) lds[y * P + t2 + N2 * k1] = v[k1];
+  }
+  __syncthreads();
+  for (int task = tid; task < R * N1; task += NT) {
+    const int y = task % R, k1 = task / R;
+    cx<T> v[N2];
+#pragma unroll
+    for (int t = 0; t < N2; ++t) v[t] = lds[y * P + t + N2 * k1];
+    dft<N2, false>(v);
+#pragma unroll
+    for (int t = 0; t < N2; ++t) lds[y * P + t + N2 * k1] = v[t];
+  }
+  __syncthreads();
+  cx<T>* __restrict__ out = S + (int64_t)p * npts + row0;
+  for (int e = tid; e < R * N; e += NT) out[e] = lds[(e / N) * P + (e % N)];
+}
+
+// Inverse z transform of position-ordered rows to natural order.
+template <typename T, int N>
+__global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
+    cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts) {
+  constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
+  constexpr int NT = row_threads<N>(), R = kRowsPerBlock;
+  __shared__ cx<T> lds[R * P];
+  constexpr int nrb = N * N / R;
+  const int rb = blockIdx.x % nrb, p = blockIdx.x / nrb;
+  const int tid = threadIdx.x, t2 = tid % N2;
+  cx<T> w[N1];
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) w[k1] = tw[t2 * k1];
+  cx<T>* __restrict__ io = S + (int64_t)p * npts + (int64_t)rb * R * N;
+  for (int e = tid; e < R * N; e += NT) lds[(e / N) * P + (e % N)] = io[e];
+  __syncthreads();
+  for (int task = tid; task < R * N1; task += NT) {
+    const int y = task % R, k1 = task / R;
+    cx<T> v[N2];
+#pragma unroll
+    for (int t = 0; t < N2; ++t) v[t] = lds[y * P + t + N2 * k1];
+    dft<N2, true>(v);
+#pragma unroll
+    for (int t = 0; t < N2; ++t) lds[y * P + t + N2 * k1] = v[t];
+  }
+  __syncthreads();
+  for (int task = tid; task < R * N2; task += NT) {
+    const int y = task / N2;
+    cx<T> v[N1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[y * P + t2 + N2 * k1], w[k1]);
+    dft<N1, true>(v);
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) io[y * N + t2 + N2 * j1] = v[j1];
+  }
+}
+
+// ------------------------------------------------------------------ strided lines
+// A workgroup owns C lines that are adjacent in memory (consecutive z
+// positions) and runs length-N transforms along a strided axis:
+//   MODE_POISSON : x lines, forward, * K / N, inverse (in place);
+//   MODE_ENERGY  : x lines, forward, sum K |Z|^2 (S unchanged);
+//   MODE_FWD     : y lines, forward only, written in position order;
+//   MODE_INV     : y lines, inverse only, natural order.
+enum { MODE_POISSON = 0, MODE_ENERGY = 1, MODE_FWD = 2, MODE_INV = 3 };
+
+template <typename T>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // fixed-order reduction: wave shuffles, then wave partials in LDS
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += red[i];
+  }
+  return s;
+}
+
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(line_threads<N>()) void k_lines(
+    cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts, int64_t estride,
+    int64_t ostride, T g0, T g1, T g2, T kscale, double* __restrict__ part) {
+  constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2;
+  constexpr int C = line_chunk<N>(), NT = line_threads<N>(), NCH = N / C;
+  __shared__ cx<T> lds[N * C];
+  __shared__ cx<T> stw[N];
+  __shared__ double red[NT / 64 + 1];
+  const int bid = blockIdx.x;
+  const int chunk = bid % NCH;
+  const int outer = (bid / NCH) % N;
+  const int p = bid / (NCH * N);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) stw[i] = tw[i];
+  cx<T>* __restrict__ base = S + (int64_t)p * npts + (int64_t)outer * ostride + chunk * C;
+  __syncthreads();
+
+  if constexpr (MODE != MODE_INV) {
+    // forward step 1: global -> LDS, tasks (c, t2) with c fastest
+    for (int task = tid; task < C * N2; task += NT) {
+      const int c = task % C, t2 = task / C;
+      cx<T> v[N1];
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) v[j1] = base[(int64_t)(t2 + N2 * j1) * estride + c];
+      dft<N1, false>(v);
+#pragma unroll
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[t2 * k1]);
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * C + c] = v[k1];
+    }
+    __syncthreads();
+    double acc = 0.0;
+    const int ky = freq_of_pos<N>(outer);
+    for (int task = tid; task < C * N1; task += NT) {
+      const int c = task % C, k1 = task / C;
+      cx<T> v[N2];
+#pragma unroll
+      for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * C + c];
+      dft<N2, false>(v);
+      if constexpr (MODE == MODE_FWD) {
+#pragma unroll
+        for (int t = 0; t < N2; ++t) base[(int64_t)(t + N2 * k1) * estride + c] = v[t];
+      } else {
+        const int kz = freq_of_pos<N>(chunk * C + c);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+          const T kk = coulomb_k<T, N>(k1 + N1 * k2, ky, kz, g0, g1, g2, kscale);
+          if constexpr (MODE == MODE_POISSON) {
+            v[k2] = scale(v[k2], kk);
+          } else {
+            acc += double(kk) * (double(v[k2].re) * double(v[k2].re) +
+                                 double(v[k2].im) * double(v[k2].im));
+          }
+        }
+        if constexpr (MODE == MODE_POISSON) {
+          dft<N2, true>(v);
+#pragma unroll
+          for (int t = 0; t < N2; ++t) lds[(t + N2 * k1) * C + c] = v[t];
+        }
+      }
+    }
+    if constexpr (MODE == MODE_ENERGY) {
+      const double s = block_sum<T>(acc, red);
+      if (tid == 0) part[bid] = s;
+      return;
+    }
+    if constexpr (MODE == MODE_FWD) return;
+    __syncthreads();
+  } else {
+    // inverse step 2: global positions -> LDS
+    for (int task = tid; task < C * N1; task += NT) {
+      const int c = task % C, k1 = task / C;
+      cx<T> v[N2];
+#pragma unroll
+      for (int t = 0; t < N2; ++t) v[t] = base[(int64_t)(t + N2 * k1) * estride + c];
+      dft<N2, true>(v);
+#pragma unroll
+      for (int t = 0; t < N2; ++t) lds[(t + N2 * k1) * C + c] = v[t];
+    }
+    __syncthreads();
+  }
+  // inverse step 1: LDS -> global natural order
+  for (int task = tid; task < C * N2; task += NT) {
+    const int c = task % C, t2 = task / C;
+    cx<T> v[N1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[(t2 + N2 * k1) * C + c], stw[t2 * k1]);
+    dft<N1, true>(v);
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) base[(int64_t)(t2 + N2 * j1) * estride + c] = v[j1];
+  }
+}
+
+// ------------------------------------------------------------------ W accumulation
+// One thread per grid point; the tile's pairs are visited in a fixed order
+// (no atomics), so W is bitwise reproducible.
+template <typename TS, int B, bool DIAG>
+__global__ __launch_bounds__(256) void k_accumulate(
+    const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W,
+    const int16_t* __restrict__ slots, int i0, int j0, int bi, int bj, double alpha,
+    int64_t npts) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= npts) return;
+  double phI[B], accI[B];
+  double phJ[DIAG ? 1 : B], accJ[DIAG ? 1 : B];
+#pragma unroll
+  for (int a = 0; a < B; ++a) {
+    phI[a] = a < bi ? phi[(int64_t)(i0 + a) * npts + r] : 0.0;
+    accI[a] = 0.0;
+  }
+  if constexpr (!DIAG) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      phJ[b] = b < bj ? phi[(int64_t)(j0 + b) * npts + r] : 0.0;
+      accJ[b] = 0.0;
+    }
+  }
+  const TS* __restrict__ Sf = reinterpret_cast<const TS*>(S);
+#pragma unroll
+  for (int a = 0; a < B; ++a) {
+#pragma unroll
+    for (int b = DIAG ? a : 0; b < B; ++b) {
+      const int s = slots[a * B + b];
+      if (s >= 0) {
+        const double v = double(Sf[2 * ((int64_t)(s >> 1) * npts + r) + (s & 1)]);
+        if constexpr (DIAG) {
+          accI[a] += v * phI[b];
+          if (a != b) accI[b] += v * phI[a];
+        } else {
+          accI[a] += v * phJ[b];
+          accJ[b] += v * phI[a];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+    if (a < bi) W[(int64_t)(i0 + a) * npts + r] -= alpha * accI[a];
+  if constexpr (!DIAG) {
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+      if (b < bj) W[(int64_t)(j0 + b) * npts + r] -= alpha * accJ[b];
+  }
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_energy_reduce(const double* __restrict__ part, int parts, double factor,
+                                double* __restrict__ e_pack) {
+  __shared__ double red[16];
+  const int p = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < parts; i += blockDim.x) acc += part[(int64_t)p * parts + i];
+  const double s = block_sum<double>(acc, red);
+  if (threadIdx.x == 0) e_pack[p] = s * factor;
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, double v, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < count; k += stride) p[k] = v;
+}
+
+__global__ void k_cast_f64_f32(const double* __restrict__ in, float* __restrict__ out,
+                               int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < count; k += stride) out[k] = float(in[k]);
+}
+
+// ------------------------------------------------------------------ dispatch
+
+#define ACEX_SIZES(X) \
+  X(16) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(120) X(128) X(144) X(160) X(192)
+
+bool supported_n(int n) {
+  switch (n) {
+#define X(N) case N:
+    ACEX_SIZES(X)
+#undef X
+    return true;
+    default: return false;
+  }
+}
+
+template <typename T>
+static bool plane_fits_t(int n) {
+  switch (n) {
+#define X(N) \
+  case N: return plane_ok<T, N>();
+    ACEX_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
+bool plane_fits(int n, int prec) { return prec == 0 ? plane_fits_t<double>(n) : plane_fits_t<float>(n); }
+
+int energy_parts_per_pack(int n) {
+  switch (n) {
+#define X(N) \
+  case N: return N * (N / line_chunk<N>());
+    ACEX_SIZES(X)
+#undef X
+    default: return 0;
+  }
+}
+
+template <typename T, int N>
+static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs, int npack,
+                           void* S, hipStream_t s) {
+  const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
+  if constexpr (plane_ok<T, N>()) {
+    hipLaunchKernelGGL((k_plane_fwd<T, N>), dim3(N * npack), dim3(plane_threads<N>()), 0, s,
+                       static_cast<const T*>(phi), packs, tw, static_cast<cx<T>*>(S), npack,
+                       g.npts);
+  } else {
+    hipLaunchKernelGGL((k_rows_fwd<T, N>), dim3((N * N / kRowsPerBlock) * npack),
+                       dim3(row_threads<N>()), 0, s, static_cast<const T*>(phi), packs, tw,
+                       static_cast<cx<T>*>(S), npack, g.npts);
+    hipLaunchKernelGGL((k_lines<T, N, MODE_FWD>), dim3((N / line_chunk<N>()) * N * npack),
+                       dim3(line_threads<N>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts,
+                       (int64_t)N, (int64_t)N * N, T(0), T(0), T(0), T(0), (double*)nullptr);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t inv_yz_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
+  const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
+  if constexpr (plane_ok<T, N>()) {
+    hipLaunchKernelGGL((k_plane_inv<T, N>), dim3(N * npack), dim3(plane_threads<N>()), 0, s,
+                       static_cast<cx<T>*>(S), tw, npack, g.npts);
+  } else {
+    hipLaunchKernelGGL((k_lines<T, N, MODE_INV>), dim3((N / line_chunk<N>()) * N * npack),
+                       dim3(line_threads<N>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts,
+                       (int64_t)N, (int64_t)N * N, T(0), T(0), T(0), T(0), (double*)nullptr);
+    hipLaunchKernelGGL((k_rows_inv<T, N>), dim3((N * N / kRowsPerBlock) * npack),
+                       dim3(row_threads<N>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int N, int MODE>
+static hipError_t x_t(const GridArgs& g, void* S, int npack, double* part, hipStream_t s) {
+  const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
+  hipLaunchKernelGGL((k_lines<T, N, MODE>), dim3((N / line_chunk<N>()) * N * npack),
+                     dim3(line_threads<N>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts,
+                     (int64_t)N * N, (int64_t)N, T(g.g2[0]), T(g.g2[1]), T(g.g2[2]),
+                     T(g.kscale), part);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_yz(const GridArgs& g, const void* phi, const Pack* packs, int npack,
+                         void* S, hipStream_t s) {
+  if (npack <= 0) return hipSuccess;
+  switch (g.n) {
+#define X(N)                                                                   \
+  case N:                                                                      \
+    return g.prec == 0 ? fwd_yz_t<double, N>(g, phi, packs, npack, S, s)       \
+                       : fwd_yz_t<float, N>(g, phi, packs, npack, S, s);
+    ACEX_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_inv_yz(const GridArgs& g, void* S, int npack, hipStream_t s) {
+  if (npack <= 0) return hipSuccess;
+  switch (g.n) {
+#define X(N) \
+  case N: return g.prec == 0 ? inv_yz_t<double, N>(g, S, npack, s) : inv_yz_t<float, N>(g, S, npack, s);
+    ACEX_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_poisson_x(const GridArgs& g, void* S, int npack, hipStream_t s) {
+  if (npack <= 0) return hipSuccess;
+  switch (g.n) {
+#define X(N)                                                              \
+  case N:                                                                 \
+    return g.prec == 0 ? x_t<double, N, MODE_POISSON>(g, S, npack, nullptr, s) \
+                       : x_t<float, N, MODE_POISSON>(g, S, npack, nullptr, s);
+    ACEX_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_energy_x(const GridArgs& g, const void* S, int npack, double* part,
+                           hipStream_t s) {
+  if (npack <= 0) return hipSuccess;
+  void* Sm = const_cast<void*>(S);
+  switch (g.n) {
+#define X(N)                                                             \
+  case N:                                                                \
+    return g.prec == 0 ? x_t<double, N, MODE_ENERGY>(g, Sm, npack, part, s) \
+                       : x_t<float, N, MODE_ENERGY>(g, Sm, npack, part, s);
+    ACEX_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename TS, int B>
+static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W,
+                        const int16_t* slots, int i0, int j0, int bi, int bj, double alpha,
+                        int64_t npts, hipStream_t s) {
+  const dim3 grid((unsigned)((npts + 255) / 256));
+  if (diag)
+    hipLaunchKernelGGL((k_accumulate<TS, B, true>), grid, dim3(256), 0, s,
+                       static_cast<const cx<TS>*>(S), phi, W, slots, i0, j0, bi, bj, alpha, npts);
+  else
+    hipLaunchKernelGGL((k_accumulate<TS, B, false>), grid, dim3(256), 0, s,
+                       static_cast<const cx<TS>*>(S), phi, W, slots, i0, j0, bi, bj, alpha, npts);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const double* phi,
+                             double* W, const int16_t* slots, int i0, int j0, int bi, int bj,
+                             double alpha, int64_t npts, hipStream_t s) {
+  if (block == 16)
+    return prec == 0 ? acc_t<double, 16>(diag, S, phi, W, slots, i0, j0, bi, bj, alpha, npts, s)
+                     : acc_t<float, 16>(diag, S, phi, W, slots, i0, j0, bi, bj, alpha, npts, s);
+  if (block == 8)
+    return prec == 0 ? acc_t<double, 8>(diag, S, phi, W, slots, i0, j0, bi, bj, alpha, npts, s)
+                     : acc_t<float, 8>(diag, S, phi, W, slots, i0, j0, bi, bj, alpha, npts, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_energy_reduce(const double* part, int npack, int parts, double factor,
+                                double* e_pack, hipStream_t s) {
+  if (npack <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_energy_reduce, dim3(npack), dim3(256), 0, s, part, parts, factor, e_pack);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_f64_f32(const double* in, float* out, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_cast_f64_f32, dim3((unsigned)blocks), dim3(256), 0, s, in, out, count);
+  return hipGetLastError();
+}
+
+}  // namespace acex

@@ -1,0 +1,134 @@
+"""The C-ABI on the host: the library loads, exports every declared call,
+and rejects bad arguments with its documented codes before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2110_07670_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ace.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:ace|exx)_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_call():
+    lib = _lib.load()
+    names = _declared()
+    assert "ace_build" in names and "ace_apply" in names and "exx_energy" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def _desc(n=32, L=10.0, k=8, prec=0, alpha=0.25, grid=None):
+    d = _lib.AceDesc()
+    g = grid or (n, n, n)
+    for a in range(3):
+        d.n[a] = g[a]
+        d.cell[a] = L
+    d.n_orb, d.precision, d.alpha = k, prec, alpha
+    return d
+
+
+def _create(d):
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    rc = lib.ace_plan_create(ctypes.byref(h), ctypes.byref(d))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(k=0), _lib.ACE_ERR_ARG),
+    (dict(L=-1.0), _lib.ACE_ERR_ARG),
+    (dict(L=float("nan")), _lib.ACE_ERR_ARG),
+    (dict(prec=7), _lib.ACE_ERR_ARG),
+    (dict(alpha=float("inf")), _lib.ACE_ERR_ARG),
+    (dict(n=56), _lib.ACE_ERR_SIZE),      # 56 = 8 * 7: prime factor 7
+    (dict(n=42), _lib.ACE_ERR_SIZE),
+    (dict(grid=(32, 32, 48)), _lib.ACE_ERR_SIZE),
+    (dict(k=5000), _lib.ACE_ERR_SIZE),
+])
+def test_plan_create_rejects(kw, code):
+    rc, h = _create(_desc(**kw))
+    assert rc == code
+    assert not h.value
+
+
+def test_plan_create_null_and_strings():
+    lib = _lib.load()
+    assert lib.ace_plan_create(None, None) == _lib.ACE_ERR_ARG
+    for c in range(6):
+        assert lib.ace_error_string(c)
+    assert lib.ace_workspace_bytes(None) == 0
+
+
+@pytest.mark.parametrize("n", [16, 24, 32, 40, 48, 64, 80, 96, 120, 128, 144, 160, 192])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_supported_grids_plan_and_workspace(n, prec):
+    lib = _lib.load()
+    rc, h = _create(_desc(n=n, k=16, prec=prec))
+    assert rc == 0
+    ws = lib.ace_workspace_bytes(h)
+    bulk = 16 if prec == 0 else 8
+    # at least the scratch of one orbital-pair tile and the overlap tables
+    assert ws >= 128 * n ** 3 * bulk
+    assert lib.ace_apply_workspace_bytes(h, 4) >= 4 * 16 * 8
+    assert lib.ace_plan_set_tiling(h, 8, 4) == 0
+    assert lib.ace_workspace_bytes(h) < ws
+    assert lib.ace_plan_set_tiling(h, 12, 0) == _lib.ACE_ERR_ARG
+    lib.ace_plan_destroy(h)
+
+
+def test_calls_validate_before_device():
+    lib = _lib.load()
+    rc, h = _create(_desc(n=16, k=4))
+    assert rc == 0
+    need = lib.ace_workspace_bytes(h)
+    N = 16 ** 3 * 4 * 8
+    # distinct fake addresses; never dereferenced because validation fails first
+    phi, W, xi, M, ex, info, ws = (0x10000000 + i * 0x1000000 for i in range(7))
+    b = lib.ace_build
+    assert b(h, None, ws, need, None, None, W, M, xi, ex, info) == _lib.ACE_ERR_ARG
+    assert b(h, None, None, need, phi, None, W, M, xi, ex, info) == _lib.ACE_ERR_ARG
+    assert b(h, None, ws, need, phi, None, phi, M, xi, ex, info) == _lib.ACE_ERR_ARG   # W aliases phi
+    assert b(h, None, ws, need, phi, None, W, M, W + 8, ex, info) == _lib.ACE_ERR_ARG  # xi overlaps W
+    assert b(h, None, ws, need - 1, phi, None, W, M, xi, ex, info) == _lib.ACE_ERR_WORKSPACE
+    assert b(None, None, ws, need, phi, None, W, M, xi, ex, info) == _lib.ACE_ERR_ARG
+    a = lib.ace_apply
+    assert a(h, None, ws, 1 << 30, xi, phi, 0, W) == _lib.ACE_ERR_ARG
+    assert a(h, None, ws, 1 << 30, xi, phi, 4, xi) == _lib.ACE_ERR_ARG
+    assert a(h, None, ws, 1, xi, phi, 4, W) == _lib.ACE_ERR_WORKSPACE
+    e = lib.exx_energy
+    assert e(h, None, ws, need, None, None, ex, None) == _lib.ACE_ERR_ARG
+    assert e(h, None, ws, need - 1, phi, None, ex, None) == _lib.ACE_ERR_WORKSPACE
+    lib.ace_plan_destroy(h)
+
+
+def test_no_device_is_reported():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a device is present; the no-device path needs a host without GPUs")
+    lib = _lib.load()
+    rc, h = _create(_desc(n=16, k=4))
+    need = lib.ace_workspace_bytes(h)
+    phi, W, xi, M, ex, info, ws = (0x10000000 + i * 0x1000000 for i in range(7))
+    assert lib.ace_build(h, None, ws, need, phi, None, W, M, xi, ex, info) == _lib.ACE_ERR_NODEV
+    assert lib.exx_energy(h, None, ws, need, phi, None, ex, None) == _lib.ACE_ERR_NODEV
+    lib.ace_plan_destroy(h)
+
+
+def test_profile_read_without_events():
+    lib = _lib.load()
+    rc, h = _create(_desc(n=16, k=4))
+    ms = (ctypes.c_double * _lib.N_STAGES)()
+    cnt = (ctypes.c_int * _lib.N_STAGES)()
+    assert lib.ace_set_profiling(h, 1) == 0
+    assert lib.ace_profile_read(h, ms, cnt) == 0
+    assert all(c == 0 for c in cnt)
+    lib.ace_plan_destroy(h)
