@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""ACE-build throughput on one MI355X: orbital-pair Poisson solves per second.
+
+One step = one ace_build (pair densities, forward transforms, Coulomb
+multiply, inverse transforms, W accumulation, M = dV Phi^T W, Cholesky,
+projectors xi, E_x = tr(M)) followed by one ace_apply of the projectors to
+the orbitals, on the 32-water-shaped workload (128 orbitals, 96^3 grid,
+L = 18.6 bohr, all 8256 pairs, FP64).  Inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line (rank 0, one GPU).  `roofline` reports the kernel that
+takes the largest share of the step, its algorithmic bytes per launch over its
+average launch time (HIP events on the library's stream, recorded during the
+timed steps), against the 8 TB/s HBM peak; `traffic` is the counter-measured
+HBM bytes per launch of that kernel from the committed rocprofv3 summary, or
+null when the kernel source changed since.  `cpu_baseline` times the FP64
+oracle's pair loop on a bounded sample of the same workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_water32_n96.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_07670_amd", "csrc", "poisson.hip")
+
+
+def tile_plan(n_orb, block):
+    """(bi, bj, diag, npack) for every tile of the unmasked schedule."""
+    out = []
+    nb = (n_orb + block - 1) // block
+    for I in range(nb):
+        for J in range(I, nb):
+            bi = min(block, n_orb - I * block)
+            bj = min(block, n_orb - J * block)
+            # two pairs of one row share a transform; a row's odd leftover is alone
+            rows = [bi - a for a in range(bi)] if I == J else [bj] * bi
+            out.append((bi, bj, I == J, sum((r + 1) // 2 for r in rows)))
+    return out
+
+
+def algorithmic_bytes(stage, tiles, npts, bulk):
+    """Compulsory HBM bytes of one step's launches of `stage` in this design.
+
+    Per packed transform (two pairs) and grid point: yz_fwd writes one
+    complex value; x_poisson reads and writes one; yz_inv reads and writes
+    one; w_accumulate reads one.  Orbital traffic is counted once per tile:
+    yz_fwd reads the tile's orbitals (8 B/pt each); w_accumulate reads them
+    and reads + writes their W rows (24 B/pt each).
+    """
+    c = 2 * bulk
+    tot = 0
+    for bi, bj, diag, npack in tiles:
+        orbs = bi if diag else bi + bj
+        if stage == "yz_fwd":
+            tot += (npack * c + orbs * 8) * npts
+        elif stage in ("x_poisson", "yz_inv"):
+            tot += npack * 2 * c * npts
+        elif stage == "w_accumulate":
+            tot += (npack * c + orbs * 24) * npts
+    return tot
+
+
+def read_traffic(stage):
+    """Counter-measured bytes per launch from the committed summary, or None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m = re.search(r"<!-- traffic-json\s*(\{.*?\})\s*-->", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != src:
+        return None
+    k = rec.get("kernels", {}).get(stage)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(system, spec, n_pairs_sample):
+    from oracle import timing
+    k = spec.n_orb
+    pairs = [(i, j) for i in range(k) for j in range(i, k)]
+    step = max(1, len(pairs) // n_pairs_sample)
+    sample = pairs[::step][:n_pairs_sample]
+    procs = timing.default_processes()
+    rate, secs, used = timing.time_pair_sample(system.phi, spec.cell, spec.alpha, sample, procs)
+    return {"value": rate, "unit": "pair-solves/s", "cores": used, "kind": "oracle",
+            "sample": "%d of %d pairs (every %d-th in i<=j order) of the same 96^3 / 128-orbital "
+                      "workload, oracle FFT pair loop with W updates, %.1f s wall on %d processes"
+                      % (len(sample), len(pairs), step, secs, used)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pairs", type=int, default=192)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device copy (for counter calibration runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        sys.exit("bench.py measures one GPU: the ACE build here runs on a single MI355X "
+                 "(--gpus %d requested; multi-GPU sharding is described, not built)" % args.gpus)
+
+    import numpy as np
+    import torch
+
+    from paper_2110_07670_amd import _lib, synth
+
+    spec = synth.config(2)
+    system = synth.build_system(spec)
+    # the host-core oracle runs before this process touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(system, spec, args.cpu_pairs)
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(system.phi).to(dev)
+    plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, "fp64", spec.alpha)
+    ws = _lib.workspace(plan.workspace_bytes(), dev)
+    ws_apply = _lib.workspace(plan.apply_workspace_bytes(spec.n_orb), dev)
+    W = torch.empty_like(phi)
+    xi = torch.empty_like(phi)
+    out = torch.empty_like(phi)
+    M = torch.empty((spec.n_orb, spec.n_orb), dtype=torch.float64, device=dev)
+    ex = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def step():
+        _lib.build_into(plan, phi, W, M, xi, ex, info, ws)
+        _lib.apply_into(plan, xi, phi, out, ws_apply)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile_read()
+    plan.set_profiling(False)
+    assert int(info.item()) == 0, "Cholesky of -M failed"
+    elapsed = t1 - t0
+    value = spec.n_pairs * args.steps / elapsed
+    ms_per_step = 1000.0 * elapsed / args.steps
+
+    tiles = tile_plan(spec.n_orb, 16)
+    npts = spec.n ** 3
+    mem_stages = ["yz_fwd", "x_poisson", "yz_inv", "w_accumulate"]
+    stages = {}
+    for name, (ms, cnt) in prof.items():
+        if cnt:
+            stages[name] = {"ms_per_step": ms / args.steps, "launches_per_step": cnt // args.steps}
+    for name in mem_stages:
+        if name in stages:
+            ab = algorithmic_bytes(name, tiles, npts, 8)
+            launch_ms = stages[name]["ms_per_step"] / stages[name]["launches_per_step"]
+            stages[name]["alg_GBps"] = ab / (stages[name]["ms_per_step"] * 1e-3) / 1e9
+            stages[name]["alg_bytes_per_launch"] = ab / stages[name]["launches_per_step"]
+            stages[name]["avg_launch_ms"] = launch_ms
+    if "m_product" in stages:
+        fl = 2.0 * spec.n_orb ** 2 * npts
+        stages["m_product"]["TFLOPs"] = fl / (stages["m_product"]["ms_per_step"] * 1e-3) / 1e12
+    if "xi_product" in stages:
+        fl = 2.0 * spec.n_orb ** 2 * npts
+        stages["xi_product"]["TFLOPs"] = fl / (stages["xi_product"]["ms_per_step"] * 1e-3) / 1e12
+    dom = max((s for s in mem_stages if s in stages), key=lambda s: stages[s]["ms_per_step"])
+    d = stages[dom]
+    achieved = d["alg_bytes_per_launch"] / (d["avg_launch_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": read_traffic(dom)}
+    pair_loop_ms = sum(stages[s]["ms_per_step"] for s in mem_stages if s in stages)
+
+    result = {
+        "metric": "orbital-pair Poisson solves/s in ACE build (128 orb, 96^3) + % HBM roofline",
+        "value": value,
+        "unit": "pair-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "water32_n96: 128 Loewdin-orthonormal sum-of-Gaussian orbitals on "
+                               "32 random rigid waters, L=18.6 bohr, 96^3 grid, all 8256 pairs, "
+                               "alpha=0.25, FP64; step = ace_build + ace_apply(xi, phi)",
+                   "n_orb": spec.n_orb, "grid": spec.n, "pairs": spec.n_pairs},
+        "roofline": roofline,
+        "pair_loop_ms": pair_loop_ms,
+        "pair_loop_alg_GBps_32B": spec.n_pairs * 32.0 * npts / (pair_loop_ms * 1e-3) / 1e9,
+        "stages": stages,
+        "ex": float(ex.item()),
+    }
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -74,7 +74,7 @@ typedef struct {
   int n[3];        /* grid points per axis; currently n1 = n2 = n3 and n in
                       {16,24,32,40,48,64,80,96,120,128,144,160,192} (factors 2, 3, 5) */
   double cell[3];  /* orthorhombic edge lengths L1, L2, L3 in bohr, > 0 */
-  int n_orb;       /* occupied orbitals, 1 .. 4096 */
+  int n_orb;       /* occupied orbitals, 1 .. 512 */
   int precision;   /* enum ace_precision */
   double alpha;    /* exact-exchange fraction (0.25 for PBE0) */
 } ace_desc;
@@ -82,7 +82,7 @@ typedef struct {
 /* Create a host-only plan for one grid / cell / orbital count.  Touches no
  * device.  Returns ACE_ERR_ARG for a null pointer, n_orb < 1, a non-positive
  * or non-finite cell edge, an unknown precision or a non-finite alpha;
- * ACE_ERR_SIZE for a grid outside the supported set or n_orb > 4096.  On
+ * ACE_ERR_SIZE for a grid outside the supported set or n_orb > 512.  On
  * success *plan owns host memory released by ace_plan_destroy. */
 int ace_plan_create(ace_plan **plan, const ace_desc *desc);
 void ace_plan_destroy(ace_plan *plan);

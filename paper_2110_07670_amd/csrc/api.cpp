@@ -120,7 +120,9 @@ bool mask_on(const uint8_t* mask, int n_orb, int i, int j) {
 }
 
 // Pair tiles for ace_build: orbital blocks of B; tile (I, J), I <= J; pairs
-// visited a-major inside a tile and packed two per transform.
+// visited a-major inside a tile.  Two pairs share one transform only when
+// they share their first orbital, (a, b) and (a, d) with d the next unmasked
+// column of row a; a row's odd leftover is a single-pair transform.
 void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& packs,
                     std::vector<int16_t>& slots, std::vector<Tile>& tiles) {
   const int B = p->block, k = p->n_orb;
@@ -138,10 +140,10 @@ void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& p
       t.diag = (I == J);
       t.pack0 = (int)packs.size();
       std::vector<int16_t> sl((size_t)B * B, int16_t(-1));
-      int half = 0;
-      Pack cur{-1, -1, -1, -1};
       int local = 0;
       for (int a = 0; a < t.bi; ++a) {
+        int half = 0;
+        Pack cur{-1, -1, -1, -1};
         for (int b = t.diag ? a : 0; b < t.bj; ++b) {
           const int i = t.i0 + a, j = t.j0 + b;
           if (!mask_on(mask, k, i, j)) continue;
@@ -158,10 +160,10 @@ void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& p
             half = 0;
           }
         }
-      }
-      if (half == 1) {
-        packs.push_back(cur);
-        ++local;
+        if (half == 1) {
+          packs.push_back(cur);
+          ++local;
+        }
       }
       t.npack = local;
       if (t.npack > 0) {
@@ -174,9 +176,10 @@ void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& p
   }
 }
 
-// Energy schedule: diagonal pairs packed with diagonal pairs and off-diagonal
-// with off-diagonal (so both halves of a transform share one weight), or one
-// pair per transform when per-pair energies are wanted.
+// Energy schedule: off-diagonal pairs (i, j), (i, j') of one row share a
+// transform (both halves then carry the weight 2); diagonal pairs are
+// single-pair transforms.  One pair per transform when per-pair energies are
+// wanted.
 void build_energy_schedule(const ace_plan* p, const uint8_t* mask, bool single,
                            std::vector<Pack>& packs, std::vector<double>& weight,
                            std::vector<int>& code) {
@@ -184,36 +187,37 @@ void build_energy_schedule(const ace_plan* p, const uint8_t* mask, bool single,
   packs.clear();
   weight.clear();
   code.clear();
-  for (int cls = 0; cls < 2; ++cls) {
+  for (int i = 0; i < k; ++i) {
+    if (mask_on(mask, k, i, i)) {
+      packs.push_back(Pack{i, i, -1, -1});
+      weight.push_back(-p->alpha);
+      code.push_back(i * k + i);
+    }
     int half = 0;
     Pack cur{-1, -1, -1, -1};
-    for (int i = 0; i < k; ++i) {
-      for (int j = i; j < k; ++j) {
-        if ((i == j) != (cls == 0)) continue;
-        if (!mask_on(mask, k, i, j)) continue;
-        const double w = -p->alpha * (i == j ? 1.0 : 2.0);
-        if (single) {
-          packs.push_back(Pack{i, j, -1, -1});
-          weight.push_back(w);
-          code.push_back(i * k + j);
-          continue;
-        }
-        if (half == 0) {
-          cur = Pack{i, j, -1, -1};
-          half = 1;
-        } else {
-          cur.c = i;
-          cur.d = j;
-          packs.push_back(cur);
-          weight.push_back(w);
-          code.push_back(-1);
-          half = 0;
-        }
+    for (int j = i + 1; j < k; ++j) {
+      if (!mask_on(mask, k, i, j)) continue;
+      if (single) {
+        packs.push_back(Pack{i, j, -1, -1});
+        weight.push_back(-2.0 * p->alpha);
+        code.push_back(i * k + j);
+        continue;
+      }
+      if (half == 0) {
+        cur = Pack{i, j, -1, -1};
+        half = 1;
+      } else {
+        cur.c = i;
+        cur.d = j;
+        packs.push_back(cur);
+        weight.push_back(-2.0 * p->alpha);
+        code.push_back(-1);
+        half = 0;
       }
     }
     if (half == 1) {
       packs.push_back(cur);
-      weight.push_back(-p->alpha * (cls == 0 ? 1.0 : 2.0));
+      weight.push_back(-2.0 * p->alpha);
       code.push_back(-1);
     }
   }
@@ -238,6 +242,22 @@ int device_present() {
     return 0;
   }
   return 1;
+}
+
+// Compute units of the current device, rounded down to a multiple of the 8
+// XCDs (persistent grids keep a workgroup on one XCD).  Cached per device.
+int device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] == 0) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cu < 8)
+      cu = 256;
+    cache[dev] = (cu / 8) * 8;
+  }
+  return cache[dev];
 }
 
 struct ProfScope {
@@ -292,7 +312,7 @@ int ace_plan_create(ace_plan** plan, const ace_desc* d) {
   if (!std::isfinite(d->alpha)) return ACE_ERR_ARG;
   if (d->n[0] != d->n[1] || d->n[1] != d->n[2]) return ACE_ERR_SIZE;
   if (!acex::supported_n(d->n[0])) return ACE_ERR_SIZE;
-  if (d->n_orb > 4096) return ACE_ERR_SIZE;
+  if (d->n_orb > 512) return ACE_ERR_SIZE;
   ace_plan* p = new ace_plan();
   p->n = d->n[0];
   for (int a = 0; a < 3; ++a) p->L[a] = d->cell[a];
@@ -412,6 +432,7 @@ int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const 
   for (int a = 0; a < 3; ++a) g.g2[a] = (kTwoPi / p->L[a]) * (kTwoPi / p->L[a]);
   g.kscale = 1.0 / (double)p->npts;
   g.tw = w + p->off_tab + o_tw;
+  g.cus = device_cus();
 
   const void* phi_bulk = phi;
   {
@@ -452,8 +473,10 @@ int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const 
     }
     {
       ProfScope ps(p, 3, s);
-      e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W, d_slots + ti * (size_t)B * B,
-                                  t.i0, t.j0, t.bi, t.bj, p->alpha, p->npts, s);
+      const bool full = pair_mask == nullptr && t.bi == B && t.bj == B;
+      e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,
+                                  full ? nullptr : d_slots + ti * (size_t)B * B, t.i0, t.j0,
+                                  t.bi, t.bj, p->alpha, p->npts, s);
       if (e != hipSuccess) return hip_fail(e);
     }
   }
@@ -557,6 +580,7 @@ int exx_energy(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const
   for (int a = 0; a < 3; ++a) g.g2[a] = (kTwoPi / p->L[a]) * (kTwoPi / p->L[a]);
   g.kscale = 1.0;
   g.tw = w + p->off_tab + o_tw;
+  g.cus = device_cus();
   const void* phi_bulk = phi;
   if (p->prec == 1) {
     ProfScope ps(p, 7, s);

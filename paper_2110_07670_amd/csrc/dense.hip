@@ -7,7 +7,7 @@
 // MFMA f64 16x16x4 operand layout (per wave, lane l):
 //   A fragment: A[i = l % 16][k = l / 16]
 //   B fragment: B[k = l / 16][j = l % 16]
-//   D (4 doubles): D[i = 4*(l / 16) + v][j = l % 16], v = 0..3
+//   D (4 doubles): D[i = l / 16 + 4 v][j = l % 16], v = 0..3
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -22,10 +22,12 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
 
 // ------------------------------------------------------------------ C = A B^T, split K
 // Workgroup: 256 threads (4 waves in 2 x 2), output tile 128 x 128, each wave
-// 64 x 64 = 4 x 4 MFMA blocks.  K staged through LDS in slabs of KT.
+// 64 x 64 = 4 x 4 MFMA blocks.  K staged through LDS in slabs of KT; the next
+// slab is loaded into registers while the current one feeds the MFMAs.
 constexpr int kAbtTile = 128;
 constexpr int kAbtKT = 16;
 constexpr int kAbtPitch = kAbtKT + 1;
+constexpr int kAbtPer = kAbtTile * kAbtKT / 256;  // elements per thread per operand
 
 __global__ __launch_bounds__(256) void k_gemm_abt(const double* __restrict__ A,
                                                   const double* __restrict__ B, int m, int n,
@@ -51,10 +53,11 @@ __global__ __launch_bounds__(256) void k_gemm_abt(const double* __restrict__ A,
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int64_t k0 = kbeg; k0 < kend; k0 += kAbtKT) {
-    // stage A[m0..m0+128)[k0..k0+KT) and B likewise; 2048 elements each
+  double ra[kAbtPer], rb[kAbtPer];
+  auto fetch = [&](int64_t k0) {
 #pragma unroll
-    for (int e = tid; e < kAbtTile * kAbtKT; e += 256) {
+    for (int q = 0; q < kAbtPer; ++q) {
+      const int e = tid + q * 256;
       const int r = e / kAbtKT, c = e % kAbtKT;
       const int64_t k = k0 + c;
       double va = 0.0, vb = 0.0;
@@ -62,14 +65,21 @@ __global__ __launch_bounds__(256) void k_gemm_abt(const double* __restrict__ A,
         if (m0 + r < m) va = A[(int64_t)(m0 + r) * K + k];
         if (n0 + r < n) vb = B[(int64_t)(n0 + r) * K + k];
       }
-      if (abs_in) {
-        va = fabs(va);
-        vb = fabs(vb);
-      }
-      sA[r * kAbtPitch + c] = va;
-      sB[r * kAbtPitch + c] = vb;
+      ra[q] = abs_in ? fabs(va) : va;
+      rb[q] = abs_in ? fabs(vb) : vb;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kAbtKT) {
+#pragma unroll
+    for (int q = 0; q < kAbtPer; ++q) {
+      const int e = tid + q * 256;
+      const int r = e / kAbtKT, c = e % kAbtKT;
+      sA[r * kAbtPitch + c] = ra[q];
+      sB[r * kAbtPitch + c] = rb[q];
     }
     __syncthreads();
+    if (k0 + kAbtKT < kend) fetch(k0 + kAbtKT);
 #pragma unroll
     for (int kk = 0; kk < kAbtKT; kk += 4) {
       double af[4], bf[4];
@@ -93,27 +103,41 @@ __global__ __launch_bounds__(256) void k_gemm_abt(const double* __restrict__ A,
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const int row = m0 + wm * 64 + i * 16 + (lane >> 4) + 4 * v;
         const int col = n0 + wn * 64 + j * 16 + (lane & 15);
         if (row < m && col < n) out[(int64_t)row * n + col] = acc[i][j][v];
       }
 }
 
-__global__ void k_reduce_splits(const double* __restrict__ partial, int nsplit, int64_t count,
-                                double scale, double* __restrict__ C, const int* __restrict__ skip) {
+// C[i] = scale * sum_s partial[s][i]: 64 outputs per workgroup, four threads
+// per output each summing a fixed residue class of s, combined in a fixed order.
+__global__ __launch_bounds__(256) void k_reduce_splits(const double* __restrict__ partial,
+                                                       int nsplit, int64_t count, double scale,
+                                                       double* __restrict__ C,
+                                                       const int* __restrict__ skip) {
   if (skip && *skip != 0) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  double s = 0.0;
-  for (int k = 0; k < nsplit; ++k) s += partial[(int64_t)k * count + i];
-  C[i] = scale * s;
+  __shared__ double red[4][64];
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + o;
+  double s0 = 0.0, s1 = 0.0;
+  if (i < count) {
+    int k = g;
+    for (; k + 4 < nsplit; k += 8) {
+      s0 += partial[(int64_t)k * count + i];
+      s1 += partial[(int64_t)(k + 4) * count + i];
+    }
+    if (k < nsplit) s0 += partial[(int64_t)k * count + i];
+  }
+  red[g][o] = s0 + s1;
+  __syncthreads();
+  if (g == 0 && i < count) C[i] = scale * ((red[0][o] + red[1][o]) + (red[2][o] + red[3][o]));
 }
 
 int gemm_abt_splits(int m, int n, int64_t K) {
   const int tiles = ((m + kAbtTile - 1) / kAbtTile) * ((n + kAbtTile - 1) / kAbtTile);
-  // aim for about 1024 workgroups, at least 4 K-slabs each
+  // aim for about 1024 workgroups, at least 8 K-slabs each
   int64_t ns = (1024 + tiles - 1) / tiles;
-  const int64_t maxs = (K + 4 * kAbtKT - 1) / (4 * kAbtKT);
+  const int64_t maxs = (K + 8 * kAbtKT - 1) / (8 * kAbtKT);
   if (ns > maxs) ns = maxs;
   if (ns < 1) ns = 1;
   return (int)ns;
@@ -128,7 +152,7 @@ hipError_t launch_gemm_abt(const double* A, const double* B, int m, int n, int64
   hipLaunchKernelGGL(k_gemm_abt, dim3(tiles_m * tiles_n, nsplit), dim3(256), 0, s, A, B, m, n, K,
                      kchunk, tiles_n, abs_inputs, partial, skip);
   const int64_t count = (int64_t)m * n;
-  hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((count + 63) / 64)), dim3(256), 0, s,
                      partial, nsplit, count, scale, C, skip);
   return hipGetLastError();
 }
@@ -136,10 +160,13 @@ hipError_t launch_gemm_abt(const double* A, const double* B, int m, int n, int64
 // ------------------------------------------------------------------ Out = A B (A small)
 // Workgroup: 256 threads, output tile 64 rows x 128 columns; wave w owns
 // rows [16 w, 16 w + 16) x 128 columns = 8 MFMA blocks.  Rows beyond 64 are
-// covered by more workgroups along grid y.
+// covered by more workgroups along grid y.  Next K-slab prefetched into
+// registers.
 constexpr int kAbRows = 64;
 constexpr int kAbCols = 128;
 constexpr int kAbKT = 16;
+constexpr int kAbPerA = kAbRows * kAbKT / 256;
+constexpr int kAbPerB = kAbKT * kAbCols / 256;
 
 __global__ __launch_bounds__(256) void k_gemm_ab(const double* __restrict__ A,
                                                  const double* __restrict__ B, int m, int k,
@@ -154,20 +181,35 @@ __global__ __launch_bounds__(256) void k_gemm_ab(const double* __restrict__ A,
   d4 acc[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < k; k0 += kAbKT) {
-    for (int e = tid; e < kAbRows * kAbKT; e += 256) {
+  double ra[kAbPerA], rb[kAbPerB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < kAbPerA; ++q) {
+      const int e = tid + q * 256;
       const int r = e / kAbKT, c = e % kAbKT;
-      double v = 0.0;
-      if (m0 + r < m && k0 + c < k) v = A[(int64_t)(m0 + r) * k + k0 + c];
-      sA[r * (kAbKT + 1) + c] = v;
+      ra[q] = (m0 + r < m && k0 + c < k) ? A[(int64_t)(m0 + r) * k + k0 + c] : 0.0;
     }
-    for (int e = tid; e < kAbKT * kAbCols; e += 256) {
+#pragma unroll
+    for (int q = 0; q < kAbPerB; ++q) {
+      const int e = tid + q * 256;
       const int kr = e / kAbCols, c = e % kAbCols;
-      double v = 0.0;
-      if (k0 + kr < k && r0 + c < R) v = B[(int64_t)(k0 + kr) * R + r0 + c];
-      sB[kr * kAbCols + c] = v;
+      rb[q] = (k0 + kr < k && r0 + c < R) ? B[(int64_t)(k0 + kr) * R + r0 + c] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < k; k0 += kAbKT) {
+#pragma unroll
+    for (int q = 0; q < kAbPerA; ++q) {
+      const int e = tid + q * 256;
+      sA[(e / kAbKT) * (kAbKT + 1) + e % kAbKT] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kAbPerB; ++q) {
+      const int e = tid + q * 256;
+      sB[(e / kAbCols) * kAbCols + e % kAbCols] = rb[q];
     }
     __syncthreads();
+    if (k0 + kAbKT < k) fetch(k0 + kAbKT);
 #pragma unroll
     for (int kk = 0; kk < kAbKT; kk += 4) {
       const double af = sA[(wave * 16 + (lane & 15)) * (kAbKT + 1) + kk + (lane >> 4)];
@@ -183,7 +225,7 @@ __global__ __launch_bounds__(256) void k_gemm_ab(const double* __restrict__ A,
   for (int j = 0; j < 8; ++j)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = m0 + wave * 16 + 4 * (lane >> 4) + v;
+      const int row = m0 + wave * 16 + (lane >> 4) + 4 * v;
       const int64_t col = r0 + j * 16 + (lane & 15);
       if (row < m && col < R) Out[(int64_t)row * R + col] = scale * acc[j][v];
     }
@@ -197,61 +239,99 @@ hipError_t launch_gemm_ab(const double* A, const double* B, int m, int k, int64_
 }
 
 // ------------------------------------------------------------------ Cholesky and L^{-1}
-// One workgroup.  Right-looking: for column j, pivot d = A[j][j] (already
-// updated), L[j][j] = sqrt(d), scale the column, update the trailing lower
-// triangle.  A non-positive (or NaN) pivot stops with info = j + 1.
-__global__ __launch_bounds__(1024) void k_cholesky(const double* __restrict__ M, int n,
-                                                   double* __restrict__ L, int* __restrict__ info) {
-  const int tid = threadIdx.x;
+// One workgroup of 1024 threads.  The matrix lives in LDS when n <= 128 and
+// in the Linv output buffer otherwise.
+//  1. A = -M (lower triangle read).
+//  2. Right-looking Cholesky: pivot d = A[j][j]; a non-positive (or NaN)
+//     pivot stops with info = j + 1; L[j][j] = sqrt(d); scale the column;
+//     update the trailing lower triangle.
+//  3. L -> global.
+//  4. In-place inverse, columns from the last: with X = L^{-1} already in the
+//     trailing block, X[j][j] = 1 / L[j][j] and
+//     X[i][j] = -X[j][j] sum_{k=j+1..i} X[i][k] L[k][j]  (i > j);
+//     eight threads share each dot product (fixed-order shuffle sum).
+constexpr int kCholLdsN = 128;
+constexpr int kCholMaxN = 512;
+
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ M, int n,
+                                                   double* __restrict__ L,
+                                                   double* __restrict__ Linv,
+                                                   int* __restrict__ info) {
+  __shared__ double smat[LDS ? kCholLdsN * (kCholLdsN + 1) : 1];
+  __shared__ double col[kCholMaxN];
   __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int P = LDS ? n + 1 : n;
+  double* A = LDS ? smat : Linv;
   for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
     const int i = (int)(e / n), j = (int)(e % n);
-    L[e] = (j <= i) ? -M[e] : 0.0;
+    A[(int64_t)i * P + j] = (j <= i) ? -M[e] : 0.0;
   }
   if (tid == 0) bad = 0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    const double d = L[(int64_t)j * n + j];
+    const double d = A[(int64_t)j * P + j];
     if (!(d > 0.0)) {
       if (tid == 0) bad = j + 1;
       break;
     }
     const double ljj = sqrt(d);
     __syncthreads();
-    if (tid == 0) L[(int64_t)j * n + j] = ljj;
-    for (int i = j + 1 + tid; i < n; i += 1024) L[(int64_t)i * n + j] /= ljj;
+    if (tid == 0) A[(int64_t)j * P + j] = ljj;
+    for (int i = j + 1 + tid; i < n; i += 1024) A[(int64_t)i * P + j] /= ljj;
     __syncthreads();
     const int rem = n - j - 1;
     for (int64_t e = tid; e < (int64_t)rem * rem; e += 1024) {
       const int ii = (int)(e / rem), kk = (int)(e % rem);
       if (kk > ii) continue;
       const int i = j + 1 + ii, k = j + 1 + kk;
-      L[(int64_t)i * n + k] -= L[(int64_t)i * n + j] * L[(int64_t)k * n + j];
+      A[(int64_t)i * P + k] -= A[(int64_t)i * P + j] * A[(int64_t)k * P + j];
     }
     __syncthreads();
   }
   __syncthreads();
-  if (tid == 0) *info = bad;
-}
-
-// Linv = L^{-1} (lower); thread j owns column j: forward substitution.
-__global__ __launch_bounds__(256) void k_tri_inv(const double* __restrict__ L, int n,
-                                                 double* __restrict__ X, const int* __restrict__ info) {
-  if (*info != 0) return;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  for (int i = 0; i < j; ++i) X[(int64_t)i * n + j] = 0.0;
-  for (int i = j; i < n; ++i) {
-    double s = (i == j) ? 1.0 : 0.0;
-    for (int k = j; k < i; ++k) s -= L[(int64_t)i * n + k] * X[(int64_t)k * n + j];
-    X[(int64_t)i * n + j] = s / L[(int64_t)i * n + i];
+  const int failed = bad;
+  if (tid == 0) *info = failed;
+  if (failed) return;
+  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    L[e] = (j <= i) ? A[(int64_t)i * P + j] : 0.0;
+  }
+  __syncthreads();
+  const int g = tid & 7, row0 = tid >> 3;  // 128 row slots, 8 threads each
+  for (int j = n - 1; j >= 0; --j) {
+    for (int k = j + 1 + tid; k < n; k += 1024) col[k] = A[(int64_t)k * P + j];
+    __syncthreads();
+    const double djj = 1.0 / A[(int64_t)j * P + j];
+    for (int i0 = j + 1; i0 < n; i0 += 128) {
+      const int i = i0 + row0;
+      double s = 0.0;
+      if (i < n)
+        for (int k = j + 1 + g; k <= i; k += 8) s += A[(int64_t)i * P + k] * col[k];
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      if (i < n && g == 0) A[(int64_t)i * P + j] = -djj * s;
+    }
+    __syncthreads();
+    if (tid == 0) A[(int64_t)j * P + j] = djj;
+    __syncthreads();
+  }
+  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (LDS) Linv[e] = (j <= i) ? A[(int64_t)i * P + j] : 0.0;
+    else if (j > i) Linv[e] = 0.0;
   }
 }
 
 hipError_t launch_cholesky_inv(const double* M, int n, double* L, double* Linv, int* info,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, M, n, L, info);
-  hipLaunchKernelGGL(k_tri_inv, dim3((n + 255) / 256), dim3(256), 0, s, L, n, Linv, info);
+  if (n > kCholMaxN) return hipErrorInvalidValue;
+  if (n <= kCholLdsN)
+    hipLaunchKernelGGL((k_chol_inv<true>), dim3(1), dim3(1024), 0, s, M, n, L, Linv, info);
+  else
+    hipLaunchKernelGGL((k_chol_inv<false>), dim3(1), dim3(1024), 0, s, M, n, L, Linv, info);
   return hipGetLastError();
 }
 

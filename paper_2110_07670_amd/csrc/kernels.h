@@ -21,6 +21,7 @@ struct GridArgs {
   double g2[3];       // (2 pi / L_a)^2 per axis
   double kscale;      // multiplies 4 pi / G^2 (1/N for the Poisson pass, 1 for energy)
   const void* tw;     // n twiddles w_n^k = exp(-2 pi i k / n), bulk precision
+  int cus;            // compute units of the device (persistent grids), a multiple of 8
 };
 
 // Does one (y, z) plane of the bulk type fit in a workgroup's LDS?
@@ -43,6 +44,7 @@ hipError_t launch_inv_yz(const GridArgs& g, void* S, int npack, hipStream_t s);
 
 // W tile update: W_I -= alpha sum_j v_ij phi_j, W_J -= alpha sum_i v_ij phi_i.
 // slots[a*B + b] = 2*pack + half (re/im) of pair (i0+a, j0+b), or -1.
+// slots == nullptr: a full unmasked B x B tile in the canonical a-major order.
 hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const double* phi,
                              double* W, const int16_t* slots, int i0, int j0, int bi, int bj,
                              double alpha, int64_t npts, hipStream_t s);

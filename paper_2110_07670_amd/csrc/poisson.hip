@@ -30,7 +30,7 @@ constexpr int kLdsBytes = 163840;
 
 template <typename T, int N>
 constexpr bool plane_ok() {
-  return (long)N * (N + 1) * (long)sizeof(cx<T>) + 64 <= kLdsBytes;
+  return ((long)N * (N + 1) + N) * (long)sizeof(cx<T>) + 64 <= kLdsBytes;
 }
 
 // threads per plane workgroup: a multiple of 64 and of N2
@@ -50,6 +50,16 @@ constexpr int plane_threads() {
     case 144: return 576;
     case 160: return 640;
     default: return 768;
+  }
+}
+
+// threads of the persistent forward plane workgroup: fewer than the inverse
+// kernel so that the prefetched orbital values of the next plane fit in
+// registers next to the transform working set.
+template <int N>
+constexpr int fwd_threads() {
+  switch (N) {
+    default: return plane_threads<N>();
   }
 }
 
@@ -75,6 +85,14 @@ constexpr int row_threads() {
   return nt;
 }
 
+// Workgroup barrier that orders LDS only: waits for this wave's LDS accesses
+// (lgkmcnt) but not for its global loads and stores, which stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename T, int N>
 __device__ __forceinline__ T coulomb_k(int kx, int ky, int kz, T g0, T g1, T g2, T kscale) {
   const int mx = kx <= N / 2 ? kx : kx - N;
@@ -85,94 +103,128 @@ __device__ __forceinline__ T coulomb_k(int kx, int ky, int kz, T g0, T g1, T g2,
 }
 
 // ------------------------------------------------------------------ y/z plane, forward
-// blockIdx -> (x, pack): consecutive block ids go to the 8 XCDs in turn, so
-// the blocks that share x (and hence the same orbital planes) land on the same
-// XCD and reuse its L2.
-__device__ __forceinline__ void plane_block(int n, int npack, int& x, int& p) {
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7;
-  const int q = bid >> 3;
+// Persistent: each workgroup walks items (x, pack) with a stride of the grid
+// size.  The orbital values of the next item are loaded into registers just
+// before the last transform step of the current item, so their latency hides
+// behind that step and behind the stores (one such workgroup fills a CU's LDS,
+// so there is no second workgroup to overlap with).  Barriers order LDS only,
+// leaving these loads and the stores in flight.
+//
+// Every pack carries pairs (a, b) and (a, d) that share their first orbital,
+// or the single pair (a, b) (c = d = -1): rho = phi_a (phi_b + i phi_d).
+template <typename T, int N>
+__device__ __forceinline__ void plane_item(int item, int npack, int& x, int& p) {
+  const int xcd = item & 7;
+  const int q = item >> 3;
   const int xh = q / npack;
   p = q - xh * npack;
   x = xcd + 8 * xh;
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_fwd(
+__global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
     const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
     cx<T>* __restrict__ S, int npack, int64_t npts) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
-  constexpr int NT = plane_threads<N>();
+  constexpr int NT = fwd_threads<N>();
+  constexpr int Q1 = (N * N2 + NT - 1) / NT;  // z-step-1 tasks per thread
   static_assert(NT % N2 == 0, "threads must be a multiple of N2");
   __shared__ cx<T> lds[N * P];
-  int x, p;
-  plane_block(N, npack, x, p);
-  const Pack pk = packs[p];
+  __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
   const int t2 = tid % N2;
-  cx<T> w[N1];
-#pragma unroll
-  for (int k1 = 0; k1 < N1; ++k1) w[k1] = tw[t2 * k1];
+  const int nitems = N * npack;
+  for (int i = tid; i < N; i += NT) stw[i] = tw[i];
+  __syncthreads();
 
-  const int64_t plane = (int64_t)x * N * N;
-  const T* __restrict__ pa = phi + (int64_t)pk.a * npts + plane;
-  const T* __restrict__ pb = phi + (int64_t)pk.b * npts + plane;
-  const bool two = pk.c >= 0;
-  const T* __restrict__ pc = phi + (int64_t)(two ? pk.c : pk.a) * npts + plane;
-  const T* __restrict__ pd = phi + (int64_t)(two ? pk.d : pk.a) * npts + plane;
-
-  // z step 1: tasks (y, t2), t2 fastest (coalesced along z)
-  for (int task = tid; task < N * N2; task += NT) {
-    const int y = task / N2;
-    cx<T> v[N1];
+  // phi_a, phi_b, phi_d of one item at this thread's z-step-1 elements
+  T fa[Q1][N1], fb[Q1][N1], fd[Q1][N1];
+  auto fetch = [&](int it) __attribute__((always_inline)) {
+    int x, p;
+    plane_item<T, N>(it, npack, x, p);
+    const Pack pk = packs[p];
+    const int64_t plane = (int64_t)x * N * N;
+    const T* __restrict__ pa = phi + (int64_t)pk.a * npts + plane;
+    const T* __restrict__ pb = phi + (int64_t)pk.b * npts + plane;
+    const T* __restrict__ pd = phi + (int64_t)(pk.c >= 0 ? pk.d : pk.b) * npts + plane;
 #pragma unroll
-    for (int j1 = 0; j1 < N1; ++j1) {
-      const int off = y * N + t2 + N2 * j1;
-      const T ra = pa[off] * pb[off];
-      const T rb = two ? pc[off] * pd[off] : T(0);
-      v[j1] = {ra, rb};
+    for (int q = 0; q < Q1; ++q) {
+      const int task = tid + q * NT;
+      const int y = (task < N * N2 ? task : 0) / N2;
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) {
+        const int off = y * N + t2 + N2 * j1;
+        fa[q][j1] = pa[off];
+        fb[q][j1] = pb[off];
+        fd[q][j1] = pd[off];
+      }
     }
-    dft<N1, false>(v);
+  };
+
+  int item = blockIdx.x;
+  if (item < nitems) fetch(item);
+  while (item < nitems) {
+    int x, p;
+    plane_item<T, N>(item, npack, x, p);
+    const T dmask = packs[p].c >= 0 ? T(1) : T(0);
+    const int64_t plane = (int64_t)x * N * N;
+    // z step 1: tasks (y, t2), t2 fastest (coalesced along z)
 #pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], w[k1]);
+    for (int q = 0; q < Q1; ++q) {
+      const int task = tid + q * NT;
+      if (task < N * N2) {
+        const int y = task / N2;
+        cx<T> v[N1];
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) lds[y * P + t2 + N2 * k1] = v[k1];
-  }
-  __syncthreads();
-  // z step 2: tasks (y, k1), y fastest
-  for (int task = tid; task < N * N1; task += NT) {
-    const int y = task % N, k1 = task / N;
-    cx<T> v[N2];
+        for (int j1 = 0; j1 < N1; ++j1)
+          v[j1] = {fa[q][j1] * fb[q][j1], fa[q][j1] * (dmask * fd[q][j1])};
+        dft<N1, false>(v);
 #pragma unroll
-    for (int t = 0; t < N2; ++t) v[t] = lds[y * P + t + N2 * k1];
-    dft<N2, false>(v);
+        for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[t2 * k1]);
 #pragma unroll
-    for (int t = 0; t < N2; ++t) lds[y * P + t + N2 * k1] = v[t];
-  }
-  __syncthreads();
-  // y step 1: tasks (pz, t2)
-  for (int task = tid; task < N * N2; task += NT) {
-    const int pz = task / N2;
-    cx<T> v[N1];
+        for (int k1 = 0; k1 < N1; ++k1) lds[y * P + t2 + N2 * k1] = v[k1];
+      }
+    }
+    lds_barrier();
+    // z step 2: tasks (y, k1), y fastest
+    for (int task = tid; task < N * N1; task += NT) {
+      const int y = task % N, k1 = task / N;
+      cx<T> v[N2];
 #pragma unroll
-    for (int j1 = 0; j1 < N1; ++j1) v[j1] = lds[(t2 + N2 * j1) * P + pz];
-    dft<N1, false>(v);
+      for (int t = 0; t < N2; ++t) v[t] = lds[y * P + t + N2 * k1];
+      dft<N2, false>(v);
 #pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], w[k1]);
+      for (int t = 0; t < N2; ++t) lds[y * P + t + N2 * k1] = v[t];
+    }
+    lds_barrier();
+    // y step 1: tasks (pz, t2)
+    for (int task = tid; task < N * N2; task += NT) {
+      const int pz = task / N2;
+      cx<T> v[N1];
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * P + pz] = v[k1];
-  }
-  __syncthreads();
-  // y step 2 -> global: tasks (pz, k1), pz fastest (coalesced)
-  cx<T>* __restrict__ out = S + (int64_t)p * npts + plane;
-  for (int task = tid; task < N * N1; task += NT) {
-    const int pz = task % N, k1 = task / N;
-    cx<T> v[N2];
+      for (int j1 = 0; j1 < N1; ++j1) v[j1] = lds[(t2 + N2 * j1) * P + pz];
+      dft<N1, false>(v);
 #pragma unroll
-    for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * P + pz];
-    dft<N2, false>(v);
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[t2 * k1]);
 #pragma unroll
-    for (int t = 0; t < N2; ++t) out[(t + N2 * k1) * N + pz] = v[t];
+      for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * P + pz] = v[k1];
+    }
+    const int next = item + gridDim.x;
+    if (next < nitems) fetch(next);
+    lds_barrier();
+    // y step 2 -> global: tasks (pz, k1), pz fastest (coalesced)
+    cx<T>* __restrict__ out = S + (int64_t)p * npts + plane;
+    for (int task = tid; task < N * N1; task += NT) {
+      const int pz = task % N, k1 = task / N;
+      cx<T> v[N2];
+#pragma unroll
+      for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * P + pz];
+      dft<N2, false>(v);
+#pragma unroll
+      for (int t = 0; t < N2; ++t) out[(t + N2 * k1) * N + pz] = v[t];
+    }
+    lds_barrier();
+    item = next;
   }
 }
 
@@ -258,15 +310,15 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
   const T* __restrict__ pa = phi + (int64_t)pk.a * npts + row0;
   const T* __restrict__ pb = phi + (int64_t)pk.b * npts + row0;
   const bool two = pk.c >= 0;
-  const T* __restrict__ pc = phi + (int64_t)(two ? pk.c : pk.a) * npts + row0;
-  const T* __restrict__ pd = phi + (int64_t)(two ? pk.d : pk.a) * npts + row0;
+  const T* __restrict__ pd = phi + (int64_t)(two ? pk.d : pk.b) * npts + row0;
   for (int task = tid; task < R * N2; task += NT) {
     const int y = task / N2;
     cx<T> v[N1];
 #pragma unroll
     for (int j1 = 0; j1 < N1; ++j1) {
       const int off = y * N + t2 + N2 * j1;
-      v[j1] = {pa[off] * pb[off], two ? pc[off] * pd[off] : T(0)};
+      const T fa = pa[off];
+      v[j1] = {fa * pb[off], two ? fa * pd[off] : T(0)};
     }
     dft<N1, false>(v);
 #pragma unroll
@@ -497,6 +549,70 @@ __global__ __launch_bounds__(256) void k_accumulate(
   }
 }
 
+// Full, unmasked tile: the schedule packs the pairs of each row a two per
+// transform, (a, b) and (a, b + 1), with a row's odd leftover alone, so the
+// pair -> (transform, half) map is known at compile time and each transform
+// is read once as one complex value.
+template <int B, bool DIAG>
+constexpr int row_packs(int a) { return DIAG ? (B - a + 1) / 2 : B / 2; }
+template <int B, bool DIAG>
+constexpr int row_pack0(int a) {
+  int s = 0;
+  for (int r = 0; r < a; ++r) s += row_packs<B, DIAG>(r);
+  return s;
+}
+
+template <typename TS, int B, bool DIAG>
+__global__ __launch_bounds__(256) void k_accumulate_full(
+    const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W, int i0,
+    int j0, double alpha, int64_t npts) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= npts) return;
+  static_assert(DIAG || B % 2 == 0, "off-diagonal rows pack evenly");
+  double phI[B], accI[B];
+  double phJ[DIAG ? 1 : B], accJ[DIAG ? 1 : B];
+#pragma unroll
+  for (int a = 0; a < B; ++a) {
+    phI[a] = phi[(int64_t)(i0 + a) * npts + r];
+    accI[a] = 0.0;
+  }
+  if constexpr (!DIAG) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      phJ[b] = phi[(int64_t)(j0 + b) * npts + r];
+      accJ[b] = 0.0;
+    }
+  }
+  sfor<0, B>([&](auto ac) {
+    constexpr int a = decltype(ac)::value;
+    sfor<0, row_packs<B, DIAG>(a)>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      constexpr int q = row_pack0<B, DIAG>(a) + c;
+      constexpr int b0 = (DIAG ? a : 0) + 2 * c;
+      const cx<TS> z = S[(int64_t)q * npts + r];
+      const double v0 = double(z.re), v1 = double(z.im);
+      if constexpr (DIAG) {
+        accI[a] += v0 * phI[b0];
+        if constexpr (b0 != a) accI[b0] += v0 * phI[a];
+        if constexpr (b0 + 1 < B) {
+          accI[a] += v1 * phI[b0 + 1];
+          accI[b0 + 1] += v1 * phI[a];
+        }
+      } else {
+        accI[a] += v0 * phJ[b0] + v1 * phJ[b0 + 1];
+        accJ[b0] += v0 * phI[a];
+        accJ[b0 + 1] += v1 * phI[a];
+      }
+    });
+  });
+#pragma unroll
+  for (int a = 0; a < B; ++a) W[(int64_t)(i0 + a) * npts + r] -= alpha * accI[a];
+  if constexpr (!DIAG) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) W[(int64_t)(j0 + b) * npts + r] -= alpha * accJ[b];
+  }
+}
+
 // ------------------------------------------------------------------ small kernels
 __global__ void k_energy_reduce(const double* __restrict__ part, int parts, double factor,
                                 double* __restrict__ e_pack) {
@@ -564,7 +680,9 @@ static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs
                            void* S, hipStream_t s) {
   const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
   if constexpr (plane_ok<T, N>()) {
-    hipLaunchKernelGGL((k_plane_fwd<T, N>), dim3(N * npack), dim3(plane_threads<N>()), 0, s,
+    const int items = N * npack;
+    const int grid = items < g.cus ? ((items + 7) / 8) * 8 : g.cus;
+    hipLaunchKernelGGL((k_plane_fwd<T, N>), dim3(grid), dim3(fwd_threads<N>()), 0, s,
                        static_cast<const T*>(phi), packs, tw, static_cast<cx<T>*>(S), npack,
                        g.npts);
   } else {
@@ -662,6 +780,15 @@ static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W,
                         const int16_t* slots, int i0, int j0, int bi, int bj, double alpha,
                         int64_t npts, hipStream_t s) {
   const dim3 grid((unsigned)((npts + 255) / 256));
+  if (slots == nullptr) {
+    if (diag)
+      hipLaunchKernelGGL((k_accumulate_full<TS, B, true>), grid, dim3(256), 0, s,
+                         static_cast<const cx<TS>*>(S), phi, W, i0, j0, alpha, npts);
+    else
+      hipLaunchKernelGGL((k_accumulate_full<TS, B, false>), grid, dim3(256), 0, s,
+                         static_cast<const cx<TS>*>(S), phi, W, i0, j0, alpha, npts);
+    return hipGetLastError();
+  }
   if (diag)
     hipLaunchKernelGGL((k_accumulate<TS, B, true>), grid, dim3(256), 0, s,
                        static_cast<const cx<TS>*>(S), phi, W, slots, i0, j0, bi, bj, alpha, npts);

@@ -52,7 +52,7 @@ def _create(d):
     (dict(n=56), _lib.ACE_ERR_SIZE),      # 56 = 8 * 7: prime factor 7
     (dict(n=42), _lib.ACE_ERR_SIZE),
     (dict(grid=(32, 32, 48)), _lib.ACE_ERR_SIZE),
-    (dict(k=5000), _lib.ACE_ERR_SIZE),
+    (dict(k=513), _lib.ACE_ERR_SIZE),
 ])
 def test_plan_create_rejects(kw, code):
     rc, h = _create(_desc(**kw))

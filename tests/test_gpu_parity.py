@@ -143,14 +143,35 @@ def test_deterministic_bitwise(lib):
         assert np.array_equal(a[key], b[key]), key
 
 
-def test_singular_overlap_sets_info(lib):
-    _say("singular M")
+def test_non_positive_overlap_sets_info(lib):
+    """-M not positive definite: the failing leading minor is reported, xi untouched.
+
+    A zero orbital gives an exactly zero third pivot; a negative exchange
+    fraction makes -M negative definite, failing at the first pivot.
+    """
+    _say("non-positive M")
+    import torch
     spec = synth.small_spec(n=16, n_orb=3, L=8.0, seed=4)
     s = synth.build_system(spec)
     phi = s.phi.copy()
-    phi[2] = phi[1]
-    plan, out = _build(lib, spec, phi)
-    assert out["info"][0] >= 1
+    phi[2] = 0.0
+    with pytest.raises(O.OracleError):
+        O.ace_build(phi, spec.cell, spec.alpha)
+    plan = lib.Plan(spec.n, (spec.L,) * 3, 3, "fp64", spec.alpha)
+    out = lib.ace_build(plan, _dev(phi))
+    torch.cuda.synchronize()
+    assert _host(out["info"])[0] == 3
+    neg = lib.Plan(spec.n, (spec.L,) * 3, 3, "fp64", -0.25)
+    xi_before = torch.full_like(_dev(s.phi), 7.0)
+    W = torch.empty_like(xi_before)
+    M = torch.empty((3, 3), dtype=torch.float64, device="cuda:0")
+    ex = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    ws = lib.workspace(neg.workspace_bytes())
+    lib.build_into(neg, _dev(s.phi), W, M, xi_before, ex, info, ws)
+    torch.cuda.synchronize()
+    assert _host(info)[0] == 1
+    assert bool((xi_before == 7.0).all())
 
 
 def test_fp32_bulk_error_bounds(lib):
