@@ -47,7 +47,12 @@ def tile_plan(n_orb, block):
     return out
 
 
-def algorithmic_bytes(stage, tiles, npts, bulk):
+def plane_fits(n, bulk):
+    """Does one (y, z) plane (plus twiddles) of the bulk type fit the 160 KiB LDS?"""
+    return (n * (n + 1) + n) * 2 * bulk + 64 <= 163840
+
+
+def algorithmic_bytes(stage, tiles, npts, bulk, plane=True):
     """Compulsory HBM bytes of one step's launches of `stage` in this design.
 
     Per packed transform (two pairs) and grid point: yz_fwd writes one
@@ -57,12 +62,17 @@ def algorithmic_bytes(stage, tiles, npts, bulk):
     and reads + writes their W rows (24 B/pt each).
     """
     c = 2 * bulk
+    # where the plane does not fit, the y/z stage is a row pass plus a column
+    # pass: one extra read and write of the complex grid each way
+    extra = 0 if plane else 2 * c
     tot = 0
     for bi, bj, diag, npack in tiles:
         orbs = bi if diag else bi + bj
         if stage == "yz_fwd":
-            tot += (npack * c + orbs * 8) * npts
-        elif stage in ("x_poisson", "yz_inv"):
+            tot += (npack * (c + extra) + orbs * 8) * npts
+        elif stage == "yz_inv":
+            tot += npack * (2 * c + extra) * npts
+        elif stage == "x_poisson":
             tot += npack * 2 * c * npts
         elif stage == "w_accumulate":
             tot += (npack * c + orbs * 24) * npts
@@ -85,6 +95,17 @@ def read_traffic(stage):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def workload_text(spec, precision):
+    if spec.name == "water32_n96" and precision == "fp64":
+        return ("water32_n96: 128 Loewdin-orthonormal sum-of-Gaussian orbitals on 32 random "
+                "rigid waters, L=18.6 bohr, 96^3 grid, all 8256 pairs, alpha=0.25, FP64; "
+                "step = ace_build + ace_apply(xi, phi)")
+    return ("%s: %d orbitals, %d^3 grid, L=%.1f bohr, all %d pairs, alpha=%.2f, %s; "
+            "step = ace_build + ace_apply(xi, phi)"
+            % (spec.name, spec.n_orb, spec.n, spec.L, spec.n_pairs, spec.alpha,
+               "FP64" if precision == "fp64" else "FP32 transforms with FP64 W/M/Cholesky/E"))
+
+
 def cpu_baseline(system, spec, n_pairs_sample):
     from oracle import timing
     k = spec.n_orb
@@ -94,9 +115,9 @@ def cpu_baseline(system, spec, n_pairs_sample):
     procs = timing.default_processes()
     rate, secs, used = timing.time_pair_sample(system.phi, spec.cell, spec.alpha, sample, procs)
     return {"value": rate, "unit": "pair-solves/s", "cores": used, "kind": "oracle",
-            "sample": "%d of %d pairs (every %d-th in i<=j order) of the same 96^3 / 128-orbital "
+            "sample": "%d of %d pairs (every %d-th in i<=j order) of the same %d^3 / %d-orbital "
                       "workload, oracle FFT pair loop with W updates, %.1f s wall on %d processes"
-                      % (len(sample), len(pairs), step, secs, used)}
+                      % (len(sample), len(pairs), step, spec.n, k, secs, used)}
 
 
 def main():
@@ -106,6 +127,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=192)
+    ap.add_argument("--config", type=int, default=2,
+                    help="workload: 2 (default, the headline), 1, 3 or 5")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for counter calibration runs)")
     args = ap.parse_args()
@@ -118,14 +142,14 @@ def main():
 
     from paper_2110_07670_amd import _lib, synth
 
-    spec = synth.config(2)
+    spec = synth.config(args.config)
     system = synth.build_system(spec)
     # the host-core oracle runs before this process touches the GPU
     cpu = None if args.no_cpu_baseline else cpu_baseline(system, spec, args.cpu_pairs)
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     phi = torch.from_numpy(system.phi).to(dev)
-    plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, "fp64", spec.alpha)
+    plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, args.precision, spec.alpha)
     ws = _lib.workspace(plan.workspace_bytes(), dev)
     ws_apply = _lib.workspace(plan.apply_workspace_bytes(spec.n_orb), dev)
     W = torch.empty_like(phi)
@@ -167,6 +191,7 @@ def main():
 
     tiles = tile_plan(spec.n_orb, 16)
     npts = spec.n ** 3
+    bulk = 8 if args.precision == "fp64" else 4
     mem_stages = ["yz_fwd", "x_poisson", "yz_inv", "w_accumulate"]
     stages = {}
     for name, (ms, cnt) in prof.items():
@@ -174,7 +199,7 @@ def main():
             stages[name] = {"ms_per_step": ms / args.steps, "launches_per_step": cnt // args.steps}
     for name in mem_stages:
         if name in stages:
-            ab = algorithmic_bytes(name, tiles, npts, 8)
+            ab = algorithmic_bytes(name, tiles, npts, bulk, plane_fits(spec.n, bulk))
             launch_ms = stages[name]["ms_per_step"] / stages[name]["launches_per_step"]
             stages[name]["alg_GBps"] = ab / (stages[name]["ms_per_step"] * 1e-3) / 1e9
             stages[name]["alg_bytes_per_launch"] = ab / stages[name]["launches_per_step"]
@@ -188,8 +213,9 @@ def main():
     dom = max((s for s in mem_stages if s in stages), key=lambda s: stages[s]["ms_per_step"])
     d = stages[dom]
     achieved = d["alg_bytes_per_launch"] / (d["avg_launch_ms"] * 1e-3) / 1e9
+    traffic = read_traffic(dom) if (args.config, args.precision) == (2, "fp64") else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": read_traffic(dom)}
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic}
     pair_loop_ms = sum(stages[s]["ms_per_step"] for s in mem_stages if s in stages)
 
     result = {
@@ -203,15 +229,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 transforms, f64 W/M/Cholesky/E",
         "data": "synthetic",
-        "config": {"workload": "water32_n96: 128 Loewdin-orthonormal sum-of-Gaussian orbitals on "
-                               "32 random rigid waters, L=18.6 bohr, 96^3 grid, all 8256 pairs, "
-                               "alpha=0.25, FP64; step = ace_build + ace_apply(xi, phi)",
+        "config": {"workload": workload_text(spec, args.precision),
                    "n_orb": spec.n_orb, "grid": spec.n, "pairs": spec.n_pairs},
         "roofline": roofline,
         "pair_loop_ms": pair_loop_ms,
-        "pair_loop_alg_GBps_32B": spec.n_pairs * 32.0 * npts / (pair_loop_ms * 1e-3) / 1e9,
+        "pair_loop_alg_GBps_32B": spec.n_pairs * 4.0 * bulk * npts / (pair_loop_ms * 1e-3) / 1e9,
         "stages": stages,
         "ex": float(ex.item()),
     }

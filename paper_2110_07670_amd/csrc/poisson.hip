@@ -187,6 +187,7 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
     }
     lds_barrier();
     // z step 2: tasks (y, k1), y fastest
+#pragma unroll 1
     for (int task = tid; task < N * N1; task += NT) {
       const int y = task % N, k1 = task / N;
       cx<T> v[N2];
@@ -210,10 +211,13 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
       for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * P + pz] = v[k1];
     }
     const int next = item + gridDim.x;
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch below the y-step-1 work
     if (next < nitems) fetch(next);
+    __builtin_amdgcn_sched_barrier(0);
     lds_barrier();
     // y step 2 -> global: tasks (pz, k1), pz fastest (coalesced)
     cx<T>* __restrict__ out = S + (int64_t)p * npts + plane;
+#pragma unroll 1
     for (int task = tid; task < N * N1; task += NT) {
       const int pz = task % N, k1 = task / N;
       cx<T> v[N2];

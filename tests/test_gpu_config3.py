@@ -1,0 +1,81 @@
+"""Config 3 (64 waters, 256 orbitals, 128^3): FP64 parity and the FP32-bulk
+errors, both against the FP64 oracle (committed reference values from
+tests/golden/make_reference.py, plus one oracle W row computed here)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ace_oracle as O
+from oracle import timing
+from paper_2110_07670_amd import synth
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+REF = os.path.join(HERE, "golden", "reference_config3.json")
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    ref = json.load(open(REF))
+    spec = synth.config(3)
+    s = synth.build_system(spec)
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    from make_reference import fingerprint_matches
+    assert fingerprint_matches(s.phi, ref["phi_fingerprint"]), "generator drift: regenerate"
+    row = 77
+    # the oracle's process pool forks before this process initialises the GPU
+    w_ref = timing.apply_vx_rows_parallel(s.phi, spec.cell, spec.alpha, [row],
+                                          timing.default_processes())[row]
+    import torch
+    from paper_2110_07670_amd import _lib
+    assert torch.cuda.is_available()
+    return spec, s, ref, row, w_ref, _lib
+
+
+def _run(setup, precision):
+    import torch
+    spec, s, ref, row, w_ref, lib = setup
+    plan = lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, precision, spec.alpha)
+    phi = torch.from_numpy(s.phi).to("cuda:0")
+    out = lib.ace_build(plan, phi)
+    back = lib.ace_apply(plan, out["xi"], phi[row:row + 1].contiguous())
+    torch.cuda.synchronize()
+    W = out["W"].cpu().numpy()
+    M = out["M"].cpu().numpy()
+    res = {"info": int(out["info"].item()), "ex": float(out["ex"].item())}
+    res["ex_err"] = abs(res["ex"] - ref["ex"])
+    res["ex_err_per_atom"] = res["ex_err"] / spec.n_atoms
+    res["M_rows_err"] = max(O.rel_err(M[int(i)], np.array(v)) for i, v in ref["M_rows"].items())
+    res["W_row_err"] = O.rel_err(W[row], w_ref)
+    res["ace_row_err"] = O.rel_err(back.cpu().numpy()[0], w_ref)
+    return res
+
+
+def test_config3_fp64_parity(setup):
+    _say("config3 fp64 n=128 orbitals=256")
+    r = _run(setup, "fp64")
+    print("config3 fp64 errors:", r, flush=True)
+    assert r["info"] == 0
+    assert r["ex_err"] < 1e-10 * abs(setup[2]["ex"])
+    assert r["M_rows_err"] < 1e-10
+    assert r["W_row_err"] < 1e-10
+    assert r["ace_row_err"] < 1e-10
+
+
+def test_config3_fp32_bulk_errors(setup):
+    """FP32 transforms, FP64 W/M/Cholesky/E: E_x within 1e-6 Ha per atom."""
+    _say("config3 fp32 n=128 orbitals=256")
+    r = _run(setup, "fp32")
+    print("config3 fp32 errors:", r, flush=True)
+    assert r["info"] == 0
+    assert r["ex_err_per_atom"] < 1e-6
+    assert r["M_rows_err"] < 1e-5
+    assert r["W_row_err"] < 1e-5
+    assert r["ace_row_err"] < 1e-5
