@@ -120,6 +120,94 @@ def cpu_baseline(system, spec, n_pairs_sample):
                       % (len(sample), len(pairs), step, spec.n, k, secs, used)}
 
 
+RHO_CUT = {2: 2.5e-2, 3: 1e-2, 5: 2e-3}  # the paper's Table 3 by system size
+
+
+def run_screened(args):
+    """Screened build vs all-pairs build on one workload (default config 5).
+
+    A screened step = Wannier moments + MLP pair predictions (or the overlap
+    integrals) + the host mask + ace_build(mask) + ace_apply.  The MLP is
+    trained beforehand (not timed) on pair energies the GPU build produces for
+    the training systems.  E_x error is judged against the all-pairs build."""
+    import numpy as np
+    import torch
+
+    from paper_2110_07670_amd import _lib, screening, synth
+
+    cfg = args.config if args.config != 2 else 5
+    spec = synth.config(cfg)
+    system = synth.build_system(spec)
+    params = None
+    dev = torch.device("cuda:0")
+    t_train = 0.0
+    if args.screen == "mlp":
+        t0 = time.perf_counter()
+        X, y = screening.training_data()
+        params = screening.train_pair_mlp(X, y)
+        t_train = time.perf_counter() - t0
+        wts = torch.from_numpy(screening.weights_to_array(params)).to(dev)
+    phi = torch.from_numpy(system.phi).to(dev)
+    plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, args.precision, spec.alpha)
+    ws = _lib.workspace(plan.workspace_bytes(), dev)
+    ws_apply = _lib.workspace(plan.apply_workspace_bytes(spec.n_orb), dev)
+    W = torch.empty_like(phi)
+    xi = torch.empty_like(phi)
+    out = torch.empty_like(phi)
+    M = torch.empty((spec.n_orb, spec.n_orb), dtype=torch.float64, device=dev)
+    ex = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    budget = 1e-6 * spec.n_atoms
+
+    def full_step():
+        _lib.build_into(plan, phi, W, M, xi, ex, info, ws)
+        _lib.apply_into(plan, xi, phi, out, ws_apply)
+
+    def screened_step():
+        if args.screen == "mlp":
+            _, feat = _lib.wannier(plan, phi)
+            pred = _lib.mlp_screen(plan, feat, wts).cpu().numpy()
+            mask = screening.mask_by_budget(pred, budget)
+        else:
+            S = _lib.overlap_integrals(plan, phi, ws).cpu().numpy()
+            mask = screening.overlap_mask(S, RHO_CUT.get(cfg, 2e-3))
+        _lib.build_into(plan, phi, W, M, xi, ex, info, ws, pair_mask=mask)
+        _lib.apply_into(plan, xi, phi, out, ws_apply)
+        return mask
+
+    full_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        full_step()
+    torch.cuda.synchronize()
+    t_full = (time.perf_counter() - t0) / args.steps
+    e_full = float(ex.item())
+    mask = screened_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mask = screened_step()
+    torch.cuda.synchronize()
+    t_scr = (time.perf_counter() - t0) / args.steps
+    e_scr = float(ex.item())
+    kept = int(mask.sum())
+    result = {
+        "metric": "screened ACE build vs all-pairs build (%s screen)" % args.screen,
+        "value": spec.n_pairs / t_scr, "unit": "pairs covered/s",
+        "solves_per_s": kept / t_scr, "all_pairs_value": spec.n_pairs / t_full,
+        "speedup": t_full / t_scr, "ms_per_step": 1000 * t_scr, "all_pairs_ms": 1000 * t_full,
+        "pairs_kept": kept, "pairs_total": spec.n_pairs,
+        "ex_all_pairs": e_full, "ex_screened": e_scr, "ex_error_Ha": abs(e_scr - e_full),
+        "ex_error_Ha_per_atom": abs(e_scr - e_full) / spec.n_atoms, "budget_Ha": budget,
+        "train_s": t_train, "steps": args.steps, "n_gpus": 1,
+        "dtype": "f64" if args.precision == "fp64" else "f32 transforms, f64 W/M/Cholesky/E",
+        "config": {"workload": workload_text(spec, args.precision), "n_orb": spec.n_orb,
+                   "grid": spec.n, "rho_cut": RHO_CUT.get(cfg) if args.screen == "overlap" else None},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,10 +220,14 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for counter calibration runs)")
+    ap.add_argument("--screen", choices=["mlp", "overlap"], default=None,
+                    help="measure a screened build against the all-pairs build instead")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU: the ACE build here runs on a single MI355X "
                  "(--gpus %d requested; multi-GPU sharding is described, not built)" % args.gpus)
+    if args.screen:
+        return run_screened(args)
 
     import numpy as np
     import torch

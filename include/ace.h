@@ -123,6 +123,32 @@ int ace_apply(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes, con
 int exx_energy(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes, const double *phi,
                const uint8_t *pair_mask, double *ex, double *pair_e);
 
+/* Pair screening (section "s-MTACE Method": pairs whose orbitals barely
+ * overlap are left out of the exchange build).  The outputs feed pair_mask.
+ *
+ * ace_overlap_integrals: S[i][j] = dV sum_r |phi_i(r)| |phi_j(r)|, the
+ *   paper's screening integral, for all i, j ([n_orb][n_orb] device double);
+ *   keeping pair (i, j) when S[i][j] >= rho_cut is the s-MTACE screen.
+ *   Needs the ace_build workspace.
+ * ace_wannier: Berry-phase moments of each orbital density,
+ *   z[i][2a], z[i][2a+1] = Re, Im of dV sum_r phi_i(r)^2 exp(2 pi i r_a / L_a)
+ *   ([n_orb][6] device double), and features feat[i] = (centre_x, centre_y,
+ *   centre_z, spread) ([n_orb][4] device double) with
+ *   centre_a = L_a/(2 pi) arg z_a in [0, L_a) and
+ *   spread^2 = sum_a (L_a/(2 pi))^2 (-ln |z_a|^2).
+ * ace_mlp_screen: for i <= j, pred[i][j] = MLP(d_ij, min(s_i, s_j),
+ *   max(s_i, s_j)) ([n_orb][n_orb] device float; entries j < i untouched),
+ *   d_ij the minimum-image distance of the centres; a 3-64-64-1 ReLU network
+ *   in FP32 predicting log10 |e_ij| of the pair energy.  weights: device
+ *   float[ace_mlp_weight_count()] laid out as mean[3] std[3] W1[64][3] b1[64]
+ *   W2[64][64] b2[64] w3[64] b3 (inputs standardised by mean and std). */
+int ace_overlap_integrals(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes,
+                          const double *phi, double *S);
+int ace_wannier(const ace_plan *plan, void *stream, const double *phi, double *z, double *feat);
+int ace_mlp_screen(const ace_plan *plan, void *stream, const double *feat, const float *weights,
+                   float *pred);
+int ace_mlp_weight_count(void);
+
 /* Static text for a status code. */
 const char *ace_error_string(int code);
 /* The hipError_t behind the calling thread's last ACE_ERR_HIP (0 if none). */

@@ -252,3 +252,53 @@ def rel_err(x: np.ndarray, ref: np.ndarray) -> float:
     ref = np.asarray(ref, dtype=np.float64)
     den = np.linalg.norm(ref.ravel())
     return float(np.linalg.norm((x - ref).ravel()) / (den if den > 0 else 1.0))
+
+
+# ----------------------------------------------------------------- learned screening inputs
+
+def wannier_moments(phi: np.ndarray, cell: np.ndarray) -> np.ndarray:
+    """z[i, a] = dV sum_r phi_i(r)^2 exp(2 pi i p_a / n_a): Berry-phase moments of
+    each orbital density on the periodic cell (orthorhombic, r_a / L_a = p_a / n_a)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    k = phi.shape[0]
+    shape = phi.shape[1:]
+    dV = cell_volume(cell) / float(np.prod(shape))
+    z = np.zeros((k, 3), dtype=np.complex128)
+    for a in range(3):
+        n = shape[a]
+        ph = np.exp(2j * math.pi * np.arange(n) / n)
+        dens = phi ** 2
+        axes = tuple(b + 1 for b in range(3) if b != a)
+        prof = dens.sum(axis=axes)          # (k, n_a)
+        z[:, a] = dV * (prof @ ph)
+    return z
+
+
+def wannier_features(z: np.ndarray, cell: np.ndarray) -> np.ndarray:
+    """(centre_x, centre_y, centre_z, spread) per orbital from the moments:
+    centre_a = L_a/(2 pi) arg z_a in [0, L_a), spread^2 = sum_a (L_a/2pi)^2 (-ln|z_a|^2)."""
+    L = np.diag(np.asarray(cell, dtype=np.float64))
+    scale = L / (2 * math.pi)
+    centre = np.mod(scale * np.angle(z), L)
+    spread = np.sqrt(np.sum(scale ** 2 * (-np.log(np.abs(z) ** 2)), axis=1))
+    return np.concatenate([centre, spread[:, None]], axis=1)
+
+
+def pair_features(feat: np.ndarray, cell: np.ndarray):
+    """For i <= j: (minimum-image centre distance, smaller spread, larger spread)."""
+    L = np.diag(np.asarray(cell, dtype=np.float64))
+    k = feat.shape[0]
+    iu, ju = np.triu_indices(k)
+    d = feat[iu, :3] - feat[ju, :3]
+    d -= L * np.rint(d / L)
+    dist = np.sqrt(np.sum(d * d, axis=1))
+    s_i, s_j = feat[iu, 3], feat[ju, 3]
+    return iu, ju, np.stack([dist, np.minimum(s_i, s_j), np.maximum(s_i, s_j)], axis=1)
+
+
+def mlp_forward(x: np.ndarray, params: dict) -> np.ndarray:
+    """y = w3 . relu(W2 relu(W1 xs + b1) + b2) + b3 with xs = (x - mean) / std."""
+    xs = (np.asarray(x, dtype=np.float64) - params["mean"]) / params["std"]
+    h1 = np.maximum(xs @ params["W1"].T + params["b1"], 0.0)
+    h2 = np.maximum(h1 @ params["W2"].T + params["b2"], 0.0)
+    return h2 @ params["w3"] + params["b3"]

@@ -24,7 +24,8 @@ STAGE_NAMES = ["yz_fwd", "x_poisson", "yz_inv", "w_accumulate", "m_product", "ch
 EXPORTS = ["ace_plan_create", "ace_plan_destroy", "ace_workspace_bytes",
            "ace_apply_workspace_bytes", "ace_build", "ace_apply", "exx_energy",
            "ace_error_string", "ace_last_hip_error", "ace_set_profiling", "ace_profile_read",
-           "ace_plan_set_tiling"]
+           "ace_plan_set_tiling", "ace_overlap_integrals", "ace_wannier", "ace_mlp_screen",
+           "ace_mlp_weight_count"]
 
 
 class AceError(RuntimeError):
@@ -77,6 +78,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ace_profile_read.restype = i
     lib.ace_plan_set_tiling.argtypes = [vp, i, i]
     lib.ace_plan_set_tiling.restype = i
+    lib.ace_overlap_integrals.argtypes = [vp, vp, vp, sz, vp, vp]
+    lib.ace_overlap_integrals.restype = i
+    lib.ace_wannier.argtypes = [vp, vp, vp, vp, vp]
+    lib.ace_wannier.restype = i
+    lib.ace_mlp_screen.argtypes = [vp, vp, vp, vp, vp]
+    lib.ace_mlp_screen.restype = i
+    lib.ace_mlp_weight_count.argtypes = []
+    lib.ace_mlp_weight_count.restype = i
     _LIB = lib
     return lib
 
@@ -221,3 +230,47 @@ def exx_energy(plan: Plan, phi, pair_mask=None, pair_energies: bool = False, ws=
                            _ptr(phi), mptr or None, _ptr(ex), _ptr(pe))
     _check(rc, "exx_energy")
     return ex, pe
+
+
+# ------------------------------------------------------------------ pair screening
+
+def overlap_integrals(plan: Plan, phi, ws=None, stream=None):
+    """S[i, j] = dV sum_r |phi_i| |phi_j| (device float64 [n_orb, n_orb])."""
+    import torch
+    S = torch.empty((plan.n_orb, plan.n_orb), dtype=torch.float64, device=phi.device)
+    if ws is None:
+        ws = workspace(plan.workspace_bytes(), phi.device)
+    rc = load().ace_overlap_integrals(plan.handle, _stream(stream), _ptr(ws),
+                                      ws.numel() * ws.element_size(), _ptr(phi), _ptr(S))
+    _check(rc, "ace_overlap_integrals")
+    return S
+
+
+def wannier(plan: Plan, phi, stream=None):
+    """(z [n_orb, 6], feat [n_orb, 4]) device float64: Berry-phase moments and
+    (centre xyz, spread) of each orbital density."""
+    import torch
+    z = torch.empty((plan.n_orb, 6), dtype=torch.float64, device=phi.device)
+    feat = torch.empty((plan.n_orb, 4), dtype=torch.float64, device=phi.device)
+    rc = load().ace_wannier(plan.handle, _stream(stream), _ptr(phi), _ptr(z), _ptr(feat))
+    _check(rc, "ace_wannier")
+    return z, feat
+
+
+def mlp_weight_count() -> int:
+    return int(load().ace_mlp_weight_count())
+
+
+def mlp_screen(plan: Plan, feat, weights, stream=None):
+    """pred [n_orb, n_orb] device float32: predicted log10 |e_ij| for i <= j
+    (entries below the diagonal are NaN)."""
+    import torch
+    w = weights if hasattr(weights, "data_ptr") else torch.from_numpy(
+        np.ascontiguousarray(weights, dtype=np.float32)).to(feat.device)
+    if w.numel() != mlp_weight_count():
+        raise ValueError("expected %d MLP weights" % mlp_weight_count())
+    pred = torch.full((plan.n_orb, plan.n_orb), float("nan"), dtype=torch.float32,
+                      device=feat.device)
+    rc = load().ace_mlp_screen(plan.handle, _stream(stream), _ptr(feat), _ptr(w), _ptr(pred))
+    _check(rc, "ace_mlp_screen")
+    return pred

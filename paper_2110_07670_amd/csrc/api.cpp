@@ -623,4 +623,40 @@ int exx_energy(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const
   return ACE_OK;
 }
 
+int ace_wannier(const ace_plan* p, void* stream, const double* phi, double* z, double* feat) {
+  if (!p || !phi || !z || !feat) return ACE_ERR_ARG;
+  if (!device_present()) return ACE_ERR_NODEV;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = acex::launch_moments(phi, p->n, p->n_orb, p->npts, p->dV, z, s);
+  if (e != hipSuccess) return hip_fail(e);
+  e = acex::launch_wannier_features(z, p->n_orb, p->L, feat, s);
+  if (e != hipSuccess) return hip_fail(e);
+  return ACE_OK;
+}
+
+int ace_overlap_integrals(const ace_plan* p, void* stream, void* ws, size_t ws_bytes,
+                          const double* phi, double* S) {
+  if (!p || !ws || !phi || !S) return ACE_ERR_ARG;
+  if (ws_bytes < p->total) return ACE_ERR_WORKSPACE;
+  if (!device_present()) return ACE_ERR_NODEV;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + p->off_part);
+  const hipError_t e = acex::launch_gemm_abt(phi, phi, p->n_orb, p->n_orb, p->npts, p->dV, S, part,
+                                             p->nsplit, true, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e);
+  return ACE_OK;
+}
+
+int ace_mlp_weight_count(void) { return acex::mlp_weight_count(); }
+
+int ace_mlp_screen(const ace_plan* p, void* stream, const double* feat, const float* weights,
+                   float* pred) {
+  if (!p || !feat || !weights || !pred) return ACE_ERR_ARG;
+  if (!device_present()) return ACE_ERR_NODEV;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const hipError_t e = acex::launch_mlp_pairs(feat, p->n_orb, p->L, weights, pred, s);
+  if (e != hipSuccess) return hip_fail(e);
+  return ACE_OK;
+}
+
 }  // extern "C"

@@ -80,4 +80,14 @@ hipError_t launch_scatter_pair_energies(const double* e_pack, const int* pair_of
                                         int npack, int n_orb, double weight_scale,
                                         double* pair_e, hipStream_t s);
 
+// Pair screening (screen.hip): Berry-phase moments z[orb][6], Wannier
+// features feat[orb][4] = (centre xyz, spread), MLP pair predictions.
+hipError_t launch_moments(const double* phi, int n, int n_orb, int64_t npts, double dV, double* z,
+                          hipStream_t s);
+hipError_t launch_wannier_features(const double* z, int n_orb, const double* L, double* feat,
+                                   hipStream_t s);
+int mlp_weight_count();
+hipError_t launch_mlp_pairs(const double* feat, int n_orb, const double* L, const float* wts,
+                            float* pred, hipStream_t s);
+
 }  // namespace acex

@@ -320,3 +320,45 @@ def test_overlap_screen_matches_direct_integral(small):
     assert abs(S[i, j] - direct) < 1e-13
     assert mask[i, j] == (direct >= 0.05)
     assert not mask[3, 1]
+
+
+# ----------------------------------------------------------------- screening inputs
+
+def test_wannier_centre_and_spread_of_a_gaussian():
+    """A periodised Gaussian exp(-|r-c|^2/2s^2): its density has variance s^2/2 per
+    axis, so |z_a| = exp(-(2 pi/L)^2 s^2 / 4), centre c and spread^2 = 3 s^2 / 2
+    (aliasing negligible at this resolution)."""
+    L, n, s = 16.0, 64, 1.3   # cross-image products ~ exp(-L^2 / 4 s^2) < 1e-16
+    c = (2.7, 9.1, 5.55)
+    phi = synth.gaussian_on_grid(n, L, c, s)[None]
+    phi /= math.sqrt((L / n) ** 3 * float(np.sum(phi ** 2)))  # normalised density
+    cell = _ortho((L, L, L))
+    z = O.wannier_moments(phi, cell)
+    f = O.wannier_features(z, cell)
+    assert np.allclose(f[0, :3], c, atol=1e-12)
+    k = 2 * math.pi / L
+    assert np.allclose(np.abs(z[0]), math.exp(-k * k * s * s / 4), rtol=1e-12)
+    assert abs(f[0, 3] ** 2 - 1.5 * s * s) < 1e-10
+
+
+def test_pair_features_minimum_image():
+    L = 10.0
+    feat = np.array([[0.5, 5.0, 5.0, 1.0], [9.5, 5.0, 5.0, 2.0], [5.0, 5.0, 5.0, 1.5]])
+    iu, ju, x = O.pair_features(feat, _ortho((L, L, L)))
+    row = {(int(a), int(b)): x[k] for k, (a, b) in enumerate(zip(iu, ju))}
+    assert np.allclose(row[(0, 1)], [1.0, 1.0, 2.0])
+    assert np.allclose(row[(0, 2)], [4.5, 1.0, 1.5])
+    assert np.allclose(row[(1, 1)], [0.0, 2.0, 2.0])
+
+
+def test_mlp_forward_closed_form():
+    H = 4
+    p = {"mean": np.zeros(3), "std": np.ones(3), "W1": np.zeros((H, 3)), "b1": np.zeros(H),
+         "W2": np.zeros((H, H)), "b2": np.zeros(H), "w3": np.zeros(H), "b3": -7.5}
+    x = np.array([[1.0, 2.0, 3.0], [0.0, -1.0, 5.0]])
+    assert np.allclose(O.mlp_forward(x, p), [-7.5, -7.5])
+    # one unit that passes x0 - x1 through the ReLUs
+    p["W1"][0] = [1.0, -1.0, 0.0]
+    p["W2"][0, 0] = 2.0
+    p["w3"][0] = 0.5
+    assert np.allclose(O.mlp_forward(x, p), [-7.5 + 0.0, -7.5 + 1.0])
