@@ -192,6 +192,13 @@ def run_screened(args):
     t_scr = (time.perf_counter() - t0) / args.steps
     e_scr = float(ex.item())
     kept = int(mask.sum())
+    stages = {}
+    for label, fn in (("screened", screened_step), ("all_pairs", full_step)):
+        plan.set_profiling(True)
+        fn()
+        torch.cuda.synchronize()
+        stages[label] = {k: [round(ms, 3), c] for k, (ms, c) in plan.profile_read().items() if c}
+        plan.set_profiling(False)
     result = {
         "metric": "screened ACE build vs all-pairs build (%s screen)" % args.screen,
         "value": spec.n_pairs / t_scr, "unit": "pairs covered/s",
@@ -200,7 +207,7 @@ def run_screened(args):
         "pairs_kept": kept, "pairs_total": spec.n_pairs,
         "ex_all_pairs": e_full, "ex_screened": e_scr, "ex_error_Ha": abs(e_scr - e_full),
         "ex_error_Ha_per_atom": abs(e_scr - e_full) / spec.n_atoms, "budget_Ha": budget,
-        "train_s": t_train, "steps": args.steps, "n_gpus": 1,
+        "train_s": t_train, "steps": args.steps, "n_gpus": 1, "stages_ms_launches": stages,
         "dtype": "f64" if args.precision == "fp64" else "f32 transforms, f64 W/M/Cholesky/E",
         "config": {"workload": workload_text(spec, args.precision), "n_orb": spec.n_orb,
                    "grid": spec.n, "rho_cut": RHO_CUT.get(cfg) if args.screen == "overlap" else None},

@@ -76,7 +76,8 @@ void layout(ace_plan* p) {
   p->eparts = acex::energy_parts_per_pack(p->n);
   size_t off = 0;
   p->off_tab = off;
-  p->tab_bytes = align256((size_t)npair * sizeof(Pack)) + align256((size_t)ntiles * B * B * 2) +
+  p->tab_bytes = align256((size_t)ntiles * 2 * B * sizeof(int)) +
+                 align256((size_t)npair * sizeof(Pack)) + align256((size_t)ntiles * B * B * 2) +
                  align256((size_t)p->n * 2 * bulk) + align256((size_t)npair * sizeof(int)) +
                  align256((size_t)npair * sizeof(double));
   off += align256(p->tab_bytes);
@@ -119,17 +120,65 @@ bool mask_on(const uint8_t* mask, int n_orb, int i, int j) {
   return mask == nullptr || mask[(size_t)i * n_orb + j] != 0;
 }
 
-// Pair tiles for ace_build: orbital blocks of B; tile (I, J), I <= J; pairs
-// visited a-major inside a tile.  Two pairs share one transform only when
-// they share their first orbital, (a, b) and (a, d) with d the next unmasked
-// column of row a; a row's odd leftover is a single-pair transform.
+// Orbital order for the pair tiles.  Without a mask: 0, 1, 2, ...  With a
+// mask: reverse Cuthill-McKee of the kept-pair graph (breadth-first from a
+// least-connected orbital, neighbours by increasing degree, ties by index,
+// reversed), so that kept pairs of spatially close orbitals gather in a band
+// and the tiles of consecutive blocks are dense while far tiles are empty.
+std::vector<int> pair_order(int k, const uint8_t* mask) {
+  std::vector<int> ord(k);
+  for (int i = 0; i < k; ++i) ord[i] = i;
+  if (!mask) return ord;
+  std::vector<std::vector<int>> adj(k);
+  for (int i = 0; i < k; ++i)
+    for (int j = i + 1; j < k; ++j)
+      if (mask[(size_t)i * k + j]) {
+        adj[i].push_back(j);
+        adj[j].push_back(i);
+      }
+  auto deg_less = [&](int a, int b) {
+    return adj[a].size() != adj[b].size() ? adj[a].size() < adj[b].size() : a < b;
+  };
+  for (auto& v : adj) std::sort(v.begin(), v.end(), deg_less);
+  std::vector<char> seen(k, 0);
+  std::vector<int> out;
+  out.reserve(k);
+  std::vector<int> by_deg(ord);
+  std::sort(by_deg.begin(), by_deg.end(), deg_less);
+  for (int start : by_deg) {
+    if (seen[start]) continue;
+    size_t head = out.size();
+    out.push_back(start);
+    seen[start] = 1;
+    while (head < out.size()) {
+      const int u = out[head++];
+      for (int v : adj[u])
+        if (!seen[v]) {
+          seen[v] = 1;
+          out.push_back(v);
+        }
+    }
+  }
+  std::reverse(out.begin(), out.end());
+  return out;
+}
+
+// Pair tiles for ace_build: blocks of B consecutive orbitals of `ord`; tile
+// (I, J), I <= J; pairs visited a-major inside a tile (local positions).  Two
+// pairs share one transform only when they share their first orbital, (a, b)
+// and (a, d) with d the next kept column of row a; a row's odd leftover is a
+// single-pair transform.  orbs receives, per kept tile, its 2B orbital
+// indices (I list, then J list; -1 past a partial block).
 void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& packs,
-                    std::vector<int16_t>& slots, std::vector<Tile>& tiles) {
+                    std::vector<int16_t>& slots, std::vector<int>& orbs,
+                    std::vector<Tile>& tiles) {
   const int B = p->block, k = p->n_orb;
   const int nb = (k + B - 1) / B;
+  const std::vector<int> ord = pair_order(k, mask);
   packs.clear();
   tiles.clear();
   slots.clear();
+  orbs.clear();
   for (int I = 0; I < nb; ++I) {
     for (int J = I; J < nb; ++J) {
       Tile t;
@@ -145,8 +194,8 @@ void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& p
         int half = 0;
         Pack cur{-1, -1, -1, -1};
         for (int b = t.diag ? a : 0; b < t.bj; ++b) {
-          const int i = t.i0 + a, j = t.j0 + b;
-          if (!mask_on(mask, k, i, j)) continue;
+          const int i = ord[t.i0 + a], j = ord[t.j0 + b];
+          if (!mask_on(mask, k, std::min(i, j), std::max(i, j))) continue;
           if (half == 0) {
             cur = Pack{i, j, -1, -1};
             sl[(size_t)a * B + b] = int16_t(2 * local);
@@ -169,6 +218,8 @@ void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& p
       if (t.npack > 0) {
         tiles.push_back(t);
         slots.insert(slots.end(), sl.begin(), sl.end());
+        for (int a = 0; a < B; ++a) orbs.push_back(a < t.bi ? ord[t.i0 + a] : -1);
+        for (int b = 0; b < B; ++b) orbs.push_back(b < t.bj ? ord[t.j0 + b] : -1);
       } else {
         packs.resize(t.pack0);
       }
@@ -404,19 +455,22 @@ int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const 
   // ---- A0: pair schedule (host) and tables
   std::vector<Pack> packs;
   std::vector<int16_t> slots;
+  std::vector<int> orbs;
   std::vector<Tile> tiles;
-  build_schedule(p, pair_mask, packs, slots, tiles);
+  build_schedule(p, pair_mask, packs, slots, orbs, tiles);
   const int B = p->block;
   const size_t bulk = p->prec == 0 ? 8 : 4;
   const size_t o_packs = 0;
   const size_t o_slots = o_packs + align256(std::max<size_t>(packs.size(), 1) * sizeof(Pack));
   const size_t o_tw = o_slots + align256(std::max<size_t>(slots.size(), 1) * 2);
-  const size_t tab_used = o_tw + align256((size_t)p->n * 2 * bulk);
+  const size_t o_orbs = o_tw + align256((size_t)p->n * 2 * bulk);
+  const size_t tab_used = o_orbs + align256(std::max<size_t>(orbs.size(), 1) * sizeof(int));
   if (tab_used > p->tab_bytes) return ACE_ERR_SIZE;
   std::vector<unsigned char> host(tab_used, 0);
   if (!packs.empty()) std::memcpy(host.data() + o_packs, packs.data(), packs.size() * sizeof(Pack));
   if (!slots.empty()) std::memcpy(host.data() + o_slots, slots.data(), slots.size() * 2);
   std::memcpy(host.data() + o_tw, p->tw_host.data(), p->tw_host.size());
+  if (!orbs.empty()) std::memcpy(host.data() + o_orbs, orbs.data(), orbs.size() * sizeof(int));
   {
     ProfScope ps(p, 7, s);
     e = hipMemcpyAsync(w + p->off_tab, host.data(), tab_used, hipMemcpyHostToDevice, s);
@@ -424,6 +478,7 @@ int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const 
   }
   const Pack* d_packs = reinterpret_cast<const Pack*>(w + p->off_tab + o_packs);
   const int16_t* d_slots = reinterpret_cast<const int16_t*>(w + p->off_tab + o_slots);
+  const int* d_orbs = reinterpret_cast<const int*>(w + p->off_tab + o_orbs);
 
   acex::GridArgs g;
   g.n = p->n;
@@ -475,8 +530,8 @@ int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const 
       ProfScope ps(p, 3, s);
       const bool full = pair_mask == nullptr && t.bi == B && t.bj == B;
       e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,
-                                  full ? nullptr : d_slots + ti * (size_t)B * B, t.i0, t.j0,
-                                  t.bi, t.bj, p->alpha, p->npts, s);
+                                  full ? nullptr : d_slots + ti * (size_t)B * B,
+                                  d_orbs + ti * (size_t)2 * B, t.bi, t.bj, p->alpha, p->npts, s);
       if (e != hipSuccess) return hip_fail(e);
     }
   }

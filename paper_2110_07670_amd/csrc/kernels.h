@@ -45,8 +45,9 @@ hipError_t launch_inv_yz(const GridArgs& g, void* S, int npack, hipStream_t s);
 // W tile update: W_I -= alpha sum_j v_ij phi_j, W_J -= alpha sum_i v_ij phi_i.
 // slots[a*B + b] = 2*pack + half (re/im) of pair (i0+a, j0+b), or -1.
 // slots == nullptr: a full unmasked B x B tile in the canonical a-major order.
+// orbs: the tile's 2B orbital indices (I list, then J list).
 hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const double* phi,
-                             double* W, const int16_t* slots, int i0, int j0, int bi, int bj,
+                             double* W, const int16_t* slots, const int* orbs, int bi, int bj,
                              double alpha, int64_t npts, hipStream_t s);
 
 // Pair energies from the per-workgroup partial sums.

@@ -503,25 +503,43 @@ __global__ __launch_bounds__(line_threads<N>()) void k_lines(
 
 // ------------------------------------------------------------------ W accumulation
 // One thread per grid point; the tile's pairs are visited in a fixed order
-// (no atomics), so W is bitwise reproducible.
+// (no atomics), so W is bitwise reproducible.  orbs: the tile's orbitals,
+// I list (B entries) then J list (B entries); only the first bi / bj are used.
 template <typename TS, int B, bool DIAG>
 __global__ __launch_bounds__(256) void k_accumulate(
     const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W,
-    const int16_t* __restrict__ slots, int i0, int j0, int bi, int bj, double alpha,
-    int64_t npts) {
+    const int16_t* __restrict__ slots, const int* __restrict__ orbs, int bi, int bj,
+    double alpha, int64_t npts) {
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (r >= npts) return;
+  // orbitals of the tile that take part in at least one kept pair (uniform)
+  bool useI[B], useJ[DIAG ? 1 : B];
+#pragma unroll
+  for (int a = 0; a < B; ++a) useI[a] = false;
+  if constexpr (!DIAG) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) useJ[b] = false;
+  }
+#pragma unroll
+  for (int a = 0; a < B; ++a)
+#pragma unroll
+    for (int b = DIAG ? a : 0; b < B; ++b)
+      if (slots[a * B + b] >= 0) {
+        useI[a] = true;
+        if constexpr (DIAG) useI[b] = true;
+        else useJ[b] = true;
+      }
   double phI[B], accI[B];
   double phJ[DIAG ? 1 : B], accJ[DIAG ? 1 : B];
 #pragma unroll
   for (int a = 0; a < B; ++a) {
-    phI[a] = a < bi ? phi[(int64_t)(i0 + a) * npts + r] : 0.0;
+    phI[a] = (a < bi && useI[a]) ? phi[(int64_t)orbs[a] * npts + r] : 0.0;
     accI[a] = 0.0;
   }
   if constexpr (!DIAG) {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      phJ[b] = b < bj ? phi[(int64_t)(j0 + b) * npts + r] : 0.0;
+      phJ[b] = (b < bj && useJ[b]) ? phi[(int64_t)orbs[B + b] * npts + r] : 0.0;
       accJ[b] = 0.0;
     }
   }
@@ -545,11 +563,11 @@ __global__ __launch_bounds__(256) void k_accumulate(
   }
 #pragma unroll
   for (int a = 0; a < B; ++a)
-    if (a < bi) W[(int64_t)(i0 + a) * npts + r] -= alpha * accI[a];
+    if (a < bi && useI[a]) W[(int64_t)orbs[a] * npts + r] -= alpha * accI[a];
   if constexpr (!DIAG) {
 #pragma unroll
     for (int b = 0; b < B; ++b)
-      if (b < bj) W[(int64_t)(j0 + b) * npts + r] -= alpha * accJ[b];
+      if (b < bj && useJ[b]) W[(int64_t)orbs[B + b] * npts + r] -= alpha * accJ[b];
   }
 }
 
@@ -568,8 +586,8 @@ constexpr int row_pack0(int a) {
 
 template <typename TS, int B, bool DIAG>
 __global__ __launch_bounds__(256) void k_accumulate_full(
-    const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W, int i0,
-    int j0, double alpha, int64_t npts) {
+    const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W,
+    const int* __restrict__ orbs, double alpha, int64_t npts) {
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (r >= npts) return;
   static_assert(DIAG || B % 2 == 0, "off-diagonal rows pack evenly");
@@ -577,13 +595,13 @@ __global__ __launch_bounds__(256) void k_accumulate_full(
   double phJ[DIAG ? 1 : B], accJ[DIAG ? 1 : B];
 #pragma unroll
   for (int a = 0; a < B; ++a) {
-    phI[a] = phi[(int64_t)(i0 + a) * npts + r];
+    phI[a] = phi[(int64_t)orbs[a] * npts + r];
     accI[a] = 0.0;
   }
   if constexpr (!DIAG) {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      phJ[b] = phi[(int64_t)(j0 + b) * npts + r];
+      phJ[b] = phi[(int64_t)orbs[B + b] * npts + r];
       accJ[b] = 0.0;
     }
   }
@@ -610,10 +628,10 @@ __global__ __launch_bounds__(256) void k_accumulate_full(
     });
   });
 #pragma unroll
-  for (int a = 0; a < B; ++a) W[(int64_t)(i0 + a) * npts + r] -= alpha * accI[a];
+  for (int a = 0; a < B; ++a) W[(int64_t)orbs[a] * npts + r] -= alpha * accI[a];
   if constexpr (!DIAG) {
 #pragma unroll
-    for (int b = 0; b < B; ++b) W[(int64_t)(j0 + b) * npts + r] -= alpha * accJ[b];
+    for (int b = 0; b < B; ++b) W[(int64_t)orbs[B + b] * npts + r] -= alpha * accJ[b];
   }
 }
 
@@ -781,36 +799,36 @@ hipError_t launch_energy_x(const GridArgs& g, const void* S, int npack, double* 
 
 template <typename TS, int B>
 static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W,
-                        const int16_t* slots, int i0, int j0, int bi, int bj, double alpha,
+                        const int16_t* slots, const int* orbs, int bi, int bj, double alpha,
                         int64_t npts, hipStream_t s) {
   const dim3 grid((unsigned)((npts + 255) / 256));
   if (slots == nullptr) {
     if (diag)
       hipLaunchKernelGGL((k_accumulate_full<TS, B, true>), grid, dim3(256), 0, s,
-                         static_cast<const cx<TS>*>(S), phi, W, i0, j0, alpha, npts);
+                         static_cast<const cx<TS>*>(S), phi, W, orbs, alpha, npts);
     else
       hipLaunchKernelGGL((k_accumulate_full<TS, B, false>), grid, dim3(256), 0, s,
-                         static_cast<const cx<TS>*>(S), phi, W, i0, j0, alpha, npts);
+                         static_cast<const cx<TS>*>(S), phi, W, orbs, alpha, npts);
     return hipGetLastError();
   }
   if (diag)
     hipLaunchKernelGGL((k_accumulate<TS, B, true>), grid, dim3(256), 0, s,
-                       static_cast<const cx<TS>*>(S), phi, W, slots, i0, j0, bi, bj, alpha, npts);
+                       static_cast<const cx<TS>*>(S), phi, W, slots, orbs, bi, bj, alpha, npts);
   else
     hipLaunchKernelGGL((k_accumulate<TS, B, false>), grid, dim3(256), 0, s,
-                       static_cast<const cx<TS>*>(S), phi, W, slots, i0, j0, bi, bj, alpha, npts);
+                       static_cast<const cx<TS>*>(S), phi, W, slots, orbs, bi, bj, alpha, npts);
   return hipGetLastError();
 }
 
 hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const double* phi,
-                             double* W, const int16_t* slots, int i0, int j0, int bi, int bj,
+                             double* W, const int16_t* slots, const int* orbs, int bi, int bj,
                              double alpha, int64_t npts, hipStream_t s) {
   if (block == 16)
-    return prec == 0 ? acc_t<double, 16>(diag, S, phi, W, slots, i0, j0, bi, bj, alpha, npts, s)
-                     : acc_t<float, 16>(diag, S, phi, W, slots, i0, j0, bi, bj, alpha, npts, s);
+    return prec == 0 ? acc_t<double, 16>(diag, S, phi, W, slots, orbs, bi, bj, alpha, npts, s)
+                     : acc_t<float, 16>(diag, S, phi, W, slots, orbs, bi, bj, alpha, npts, s);
   if (block == 8)
-    return prec == 0 ? acc_t<double, 8>(diag, S, phi, W, slots, i0, j0, bi, bj, alpha, npts, s)
-                     : acc_t<float, 8>(diag, S, phi, W, slots, i0, j0, bi, bj, alpha, npts, s);
+    return prec == 0 ? acc_t<double, 8>(diag, S, phi, W, slots, orbs, bi, bj, alpha, npts, s)
+                     : acc_t<float, 8>(diag, S, phi, W, slots, orbs, bi, bj, alpha, npts, s);
   return hipErrorInvalidValue;
 }
 

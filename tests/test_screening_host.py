@@ -71,6 +71,10 @@ def test_training_fits_a_smooth_decay():
     X = np.stack([rng.uniform(0, 15, 3000), rng.uniform(1, 2, 3000), rng.uniform(1, 2, 3000)], 1)
     X[:, 1], X[:, 2] = np.minimum(X[:, 1], X[:, 2]), np.maximum(X[:, 1], X[:, 2])
     y = -1.0 - 0.35 * X[:, 0] ** 2 / (X[:, 1] ** 2 + X[:, 2] ** 2)
-    p = screening.train_pair_mlp(X, y, epochs=60, seed=1)
+    p = screening.train_pair_mlp(X, y, epochs=60, seed=1, upper_quantile=None)
     rmse = float(np.sqrt(np.mean((screening.forward(X, p) - y) ** 2)))
     assert rmse < 0.25 * y.std()
+    # calibrated: the output is raised until 95% of the training pairs lie below it
+    q = screening.train_pair_mlp(X, y, epochs=60, seed=1, upper_quantile=0.95)
+    under = float(np.mean(screening.forward(X, q) < y))
+    assert 0.03 < under < 0.07
