@@ -28,6 +28,7 @@ struct Tile {
   int i0, j0, bi, bj;
   bool diag;
   int pack0, npack;
+  unsigned useI, useJ;  // local orbitals with at least one kept pair
 };
 
 struct ProfRec {
@@ -77,7 +78,7 @@ void layout(ace_plan* p) {
   size_t off = 0;
   p->off_tab = off;
   p->tab_bytes = align256((size_t)ntiles * 2 * B * sizeof(int)) +
-                 align256((size_t)npair * sizeof(Pack)) + align256((size_t)ntiles * B * B * 2) +
+                 align256((size_t)npair * sizeof(Pack)) + align256((size_t)npair * sizeof(int)) +
                  align256((size_t)p->n * 2 * bulk) + align256((size_t)npair * sizeof(int)) +
                  align256((size_t)npair * sizeof(double));
   off += align256(p->tab_bytes);
@@ -167,17 +168,18 @@ std::vector<int> pair_order(int k, const uint8_t* mask) {
 // (I, J), I <= J; pairs visited a-major inside a tile (local positions).  Two
 // pairs share one transform only when they share their first orbital, (a, b)
 // and (a, d) with d the next kept column of row a; a row's odd leftover is a
-// single-pair transform.  orbs receives, per kept tile, its 2B orbital
-// indices (I list, then J list; -1 past a partial block).
+// single-pair transform.  meta receives, per transform, the local positions
+// of its pairs (a0 | b0 << 8 | a1 << 16 | b1 << 24, a1 = 255 for a single
+// pair); orbs receives, per kept tile, its 2B orbital indices (I list, then
+// J list; -1 past a partial block).
 void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& packs,
-                    std::vector<int16_t>& slots, std::vector<int>& orbs,
-                    std::vector<Tile>& tiles) {
+                    std::vector<int>& meta, std::vector<int>& orbs, std::vector<Tile>& tiles) {
   const int B = p->block, k = p->n_orb;
   const int nb = (k + B - 1) / B;
   const std::vector<int> ord = pair_order(k, mask);
   packs.clear();
   tiles.clear();
-  slots.clear();
+  meta.clear();
   orbs.clear();
   for (int I = 0; I < nb; ++I) {
     for (int J = I; J < nb; ++J) {
@@ -188,40 +190,45 @@ void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& p
       t.bj = std::min(B, k - t.j0);
       t.diag = (I == J);
       t.pack0 = (int)packs.size();
-      std::vector<int16_t> sl((size_t)B * B, int16_t(-1));
+      t.useI = t.useJ = 0u;
       int local = 0;
       for (int a = 0; a < t.bi; ++a) {
         int half = 0;
         Pack cur{-1, -1, -1, -1};
+        int code = 0;
         for (int b = t.diag ? a : 0; b < t.bj; ++b) {
           const int i = ord[t.i0 + a], j = ord[t.j0 + b];
           if (!mask_on(mask, k, std::min(i, j), std::max(i, j))) continue;
+          t.useI |= 1u << a;
+          if (t.diag) t.useI |= 1u << b;
+          else t.useJ |= 1u << b;
           if (half == 0) {
             cur = Pack{i, j, -1, -1};
-            sl[(size_t)a * B + b] = int16_t(2 * local);
+            code = a | (b << 8);
             half = 1;
           } else {
             cur.c = i;
             cur.d = j;
-            sl[(size_t)a * B + b] = int16_t(2 * local + 1);
             packs.push_back(cur);
+            meta.push_back(code | (a << 16) | (b << 24));
             ++local;
             half = 0;
           }
         }
         if (half == 1) {
           packs.push_back(cur);
+          meta.push_back(code | (255 << 16));
           ++local;
         }
       }
       t.npack = local;
       if (t.npack > 0) {
         tiles.push_back(t);
-        slots.insert(slots.end(), sl.begin(), sl.end());
         for (int a = 0; a < B; ++a) orbs.push_back(a < t.bi ? ord[t.i0 + a] : -1);
         for (int b = 0; b < B; ++b) orbs.push_back(b < t.bj ? ord[t.j0 + b] : -1);
       } else {
         packs.resize(t.pack0);
+        meta.resize(t.pack0);
       }
     }
   }
@@ -454,21 +461,21 @@ int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const 
 
   // ---- A0: pair schedule (host) and tables
   std::vector<Pack> packs;
-  std::vector<int16_t> slots;
+  std::vector<int> meta;
   std::vector<int> orbs;
   std::vector<Tile> tiles;
-  build_schedule(p, pair_mask, packs, slots, orbs, tiles);
+  build_schedule(p, pair_mask, packs, meta, orbs, tiles);
   const int B = p->block;
   const size_t bulk = p->prec == 0 ? 8 : 4;
   const size_t o_packs = 0;
-  const size_t o_slots = o_packs + align256(std::max<size_t>(packs.size(), 1) * sizeof(Pack));
-  const size_t o_tw = o_slots + align256(std::max<size_t>(slots.size(), 1) * 2);
+  const size_t o_meta = o_packs + align256(std::max<size_t>(packs.size(), 1) * sizeof(Pack));
+  const size_t o_tw = o_meta + align256(std::max<size_t>(meta.size(), 1) * sizeof(int));
   const size_t o_orbs = o_tw + align256((size_t)p->n * 2 * bulk);
   const size_t tab_used = o_orbs + align256(std::max<size_t>(orbs.size(), 1) * sizeof(int));
   if (tab_used > p->tab_bytes) return ACE_ERR_SIZE;
   std::vector<unsigned char> host(tab_used, 0);
   if (!packs.empty()) std::memcpy(host.data() + o_packs, packs.data(), packs.size() * sizeof(Pack));
-  if (!slots.empty()) std::memcpy(host.data() + o_slots, slots.data(), slots.size() * 2);
+  if (!meta.empty()) std::memcpy(host.data() + o_meta, meta.data(), meta.size() * sizeof(int));
   std::memcpy(host.data() + o_tw, p->tw_host.data(), p->tw_host.size());
   if (!orbs.empty()) std::memcpy(host.data() + o_orbs, orbs.data(), orbs.size() * sizeof(int));
   {
@@ -477,7 +484,7 @@ int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const 
     if (e != hipSuccess) return hip_fail(e);
   }
   const Pack* d_packs = reinterpret_cast<const Pack*>(w + p->off_tab + o_packs);
-  const int16_t* d_slots = reinterpret_cast<const int16_t*>(w + p->off_tab + o_slots);
+  const int* d_meta = reinterpret_cast<const int*>(w + p->off_tab + o_meta);
   const int* d_orbs = reinterpret_cast<const int*>(w + p->off_tab + o_orbs);
 
   acex::GridArgs g;
@@ -530,8 +537,9 @@ int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const 
       ProfScope ps(p, 3, s);
       const bool full = pair_mask == nullptr && t.bi == B && t.bj == B;
       e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,
-                                  full ? nullptr : d_slots + ti * (size_t)B * B,
-                                  d_orbs + ti * (size_t)2 * B, t.bi, t.bj, p->alpha, p->npts, s);
+                                  full ? nullptr : d_meta + t.pack0, t.npack,
+                                  d_orbs + ti * (size_t)2 * B, t.useI, t.useJ, p->alpha, p->npts,
+                                  s);
       if (e != hipSuccess) return hip_fail(e);
     }
   }

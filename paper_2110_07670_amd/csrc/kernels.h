@@ -43,12 +43,15 @@ int energy_parts_per_pack(int n);
 hipError_t launch_inv_yz(const GridArgs& g, void* S, int npack, hipStream_t s);
 
 // W tile update: W_I -= alpha sum_j v_ij phi_j, W_J -= alpha sum_i v_ij phi_i.
-// slots[a*B + b] = 2*pack + half (re/im) of pair (i0+a, j0+b), or -1.
-// slots == nullptr: a full unmasked B x B tile in the canonical a-major order.
-// orbs: the tile's 2B orbital indices (I list, then J list).
+// meta[p] = a0 | b0 << 8 | a1 << 16 | b1 << 24: local positions of the pairs
+// in the real / imaginary half of transform p (a1 = 255: single pair);
+// meta == nullptr: a full unmasked B x B tile in the canonical a-major order.
+// orbs: the tile's 2B orbital indices (I list, then J list); useI / useJ:
+// local orbitals with at least one pair.
 hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const double* phi,
-                             double* W, const int16_t* slots, const int* orbs, int bi, int bj,
-                             double alpha, int64_t npts, hipStream_t s);
+                             double* W, const int* meta, int npack, const int* orbs,
+                             unsigned useI, unsigned useJ, double alpha, int64_t npts,
+                             hipStream_t s);
 
 // Pair energies from the per-workgroup partial sums.
 // e_pack[p] = sum of the parts of pack p (fixed order) * omega / N^2.

@@ -504,70 +504,76 @@ __global__ __launch_bounds__(line_threads<N>()) void k_lines(
 // ------------------------------------------------------------------ W accumulation
 // One thread per grid point; the tile's pairs are visited in a fixed order
 // (no atomics), so W is bitwise reproducible.  orbs: the tile's orbitals,
-// I list (B entries) then J list (B entries); only the first bi / bj are used.
+// I list (B entries) then J list (B entries).  General (masked) tiles: a
+// runtime loop over the tile's transforms with unconditional loads (so they
+// pipeline); meta[p] = a0 | b0 << 8 | a1 << 16 | b1 << 24 gives the local
+// positions of the pair in the real (a0, b0) and imaginary (a1, b1; a1 = 255
+// when absent) half; useI / useJ flag the orbitals with at least one pair.
+
+// arr[idx] for a uniform runtime idx, as selects over the positions (every
+// element keeps a static index, so the arrays stay in registers)
+template <int B>
+__device__ __forceinline__ double reg_get(const double (&arr)[B], int idx) {
+  double v = 0.0;
+  sfor<0, B>([&](auto c) {
+    constexpr int k = decltype(c)::value;
+    v = (idx == k) ? arr[k] : v;
+  });
+  return v;
+}
+template <int B>
+__device__ __forceinline__ void reg_add(double (&arr)[B], int idx, double v) {
+  sfor<0, B>([&](auto c) {
+    constexpr int k = decltype(c)::value;
+    arr[k] += (idx == k) ? v : 0.0;
+  });
+}
+
 template <typename TS, int B, bool DIAG>
 __global__ __launch_bounds__(256) void k_accumulate(
     const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W,
-    const int16_t* __restrict__ slots, const int* __restrict__ orbs, int bi, int bj,
-    double alpha, int64_t npts) {
+    const int* __restrict__ meta, int npack, const int* __restrict__ orbs, unsigned useI,
+    unsigned useJ, double alpha, int64_t npts) {
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (r >= npts) return;
-  // orbitals of the tile that take part in at least one kept pair (uniform)
-  bool useI[B], useJ[DIAG ? 1 : B];
-#pragma unroll
-  for (int a = 0; a < B; ++a) useI[a] = false;
-  if constexpr (!DIAG) {
-#pragma unroll
-    for (int b = 0; b < B; ++b) useJ[b] = false;
-  }
-#pragma unroll
-  for (int a = 0; a < B; ++a)
-#pragma unroll
-    for (int b = DIAG ? a : 0; b < B; ++b)
-      if (slots[a * B + b] >= 0) {
-        useI[a] = true;
-        if constexpr (DIAG) useI[b] = true;
-        else useJ[b] = true;
-      }
   double phI[B], accI[B];
   double phJ[DIAG ? 1 : B], accJ[DIAG ? 1 : B];
 #pragma unroll
   for (int a = 0; a < B; ++a) {
-    phI[a] = (a < bi && useI[a]) ? phi[(int64_t)orbs[a] * npts + r] : 0.0;
+    phI[a] = ((useI >> a) & 1u) ? phi[(int64_t)orbs[a] * npts + r] : 0.0;
     accI[a] = 0.0;
   }
   if constexpr (!DIAG) {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-      phJ[b] = (b < bj && useJ[b]) ? phi[(int64_t)orbs[B + b] * npts + r] : 0.0;
+      phJ[b] = ((useJ >> b) & 1u) ? phi[(int64_t)orbs[B + b] * npts + r] : 0.0;
       accJ[b] = 0.0;
     }
   }
-  const TS* __restrict__ Sf = reinterpret_cast<const TS*>(S);
-#pragma unroll
-  for (int a = 0; a < B; ++a) {
-#pragma unroll
-    for (int b = DIAG ? a : 0; b < B; ++b) {
-      const int s = slots[a * B + b];
-      if (s >= 0) {
-        const double v = double(Sf[2 * ((int64_t)(s >> 1) * npts + r) + (s & 1)]);
-        if constexpr (DIAG) {
-          accI[a] += v * phI[b];
-          if (a != b) accI[b] += v * phI[a];
-        } else {
-          accI[a] += v * phJ[b];
-          accJ[b] += v * phI[a];
-        }
-      }
+  auto pair = [&](int a, int b, double v) __attribute__((always_inline)) {
+    if constexpr (DIAG) {
+      reg_add<B>(accI, a, v * reg_get<B>(phI, b));
+      if (a != b) reg_add<B>(accI, b, v * reg_get<B>(phI, a));
+    } else {
+      reg_add<B>(accI, a, v * reg_get<B>(phJ, b));
+      reg_add<B>(accJ, b, v * reg_get<B>(phI, a));
     }
+  };
+#pragma unroll 4
+  for (int p = 0; p < npack; ++p) {
+    const cx<TS> z = S[(int64_t)p * npts + r];
+    const int m = meta[p];
+    const int a0 = m & 255, b0 = (m >> 8) & 255, a1 = (m >> 16) & 255, b1 = (m >> 24) & 255;
+    pair(a0, b0, double(z.re));
+    if (a1 != 255) pair(a1, b1, double(z.im));
   }
 #pragma unroll
   for (int a = 0; a < B; ++a)
-    if (a < bi && useI[a]) W[(int64_t)orbs[a] * npts + r] -= alpha * accI[a];
+    if ((useI >> a) & 1u) W[(int64_t)orbs[a] * npts + r] -= alpha * accI[a];
   if constexpr (!DIAG) {
 #pragma unroll
     for (int b = 0; b < B; ++b)
-      if (b < bj && useJ[b]) W[(int64_t)orbs[B + b] * npts + r] -= alpha * accJ[b];
+      if ((useJ >> b) & 1u) W[(int64_t)orbs[B + b] * npts + r] -= alpha * accJ[b];
   }
 }
 
@@ -798,11 +804,11 @@ hipError_t launch_energy_x(const GridArgs& g, const void* S, int npack, double* 
 }
 
 template <typename TS, int B>
-static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W,
-                        const int16_t* slots, const int* orbs, int bi, int bj, double alpha,
+static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W, const int* meta,
+                        int npack, const int* orbs, unsigned useI, unsigned useJ, double alpha,
                         int64_t npts, hipStream_t s) {
   const dim3 grid((unsigned)((npts + 255) / 256));
-  if (slots == nullptr) {
+  if (meta == nullptr) {
     if (diag)
       hipLaunchKernelGGL((k_accumulate_full<TS, B, true>), grid, dim3(256), 0, s,
                          static_cast<const cx<TS>*>(S), phi, W, orbs, alpha, npts);
@@ -813,22 +819,29 @@ static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W,
   }
   if (diag)
     hipLaunchKernelGGL((k_accumulate<TS, B, true>), grid, dim3(256), 0, s,
-                       static_cast<const cx<TS>*>(S), phi, W, slots, orbs, bi, bj, alpha, npts);
+                       static_cast<const cx<TS>*>(S), phi, W, meta, npack, orbs, useI, useJ,
+                       alpha, npts);
   else
     hipLaunchKernelGGL((k_accumulate<TS, B, false>), grid, dim3(256), 0, s,
-                       static_cast<const cx<TS>*>(S), phi, W, slots, orbs, bi, bj, alpha, npts);
+                       static_cast<const cx<TS>*>(S), phi, W, meta, npack, orbs, useI, useJ,
+                       alpha, npts);
   return hipGetLastError();
 }
 
 hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const double* phi,
-                             double* W, const int16_t* slots, const int* orbs, int bi, int bj,
-                             double alpha, int64_t npts, hipStream_t s) {
+                             double* W, const int* meta, int npack, const int* orbs,
+                             unsigned useI, unsigned useJ, double alpha, int64_t npts,
+                             hipStream_t s) {
   if (block == 16)
-    return prec == 0 ? acc_t<double, 16>(diag, S, phi, W, slots, orbs, bi, bj, alpha, npts, s)
-                     : acc_t<float, 16>(diag, S, phi, W, slots, orbs, bi, bj, alpha, npts, s);
+    return prec == 0 ? acc_t<double, 16>(diag, S, phi, W, meta, npack, orbs, useI, useJ, alpha,
+                                         npts, s)
+                     : acc_t<float, 16>(diag, S, phi, W, meta, npack, orbs, useI, useJ, alpha,
+                                        npts, s);
   if (block == 8)
-    return prec == 0 ? acc_t<double, 8>(diag, S, phi, W, slots, orbs, bi, bj, alpha, npts, s)
-                     : acc_t<float, 8>(diag, S, phi, W, slots, orbs, bi, bj, alpha, npts, s);
+    return prec == 0 ? acc_t<double, 8>(diag, S, phi, W, meta, npack, orbs, useI, useJ, alpha,
+                                        npts, s)
+                     : acc_t<float, 8>(diag, S, phi, W, meta, npack, orbs, useI, useJ, alpha,
+                                       npts, s);
   return hipErrorInvalidValue;
 }
 
