@@ -32,8 +32,9 @@
  * at their calls.
  *
  * Ownership: every array is caller-owned device memory, except pair_mask
- * (host memory).  The library never allocates device memory and never frees
- * caller memory; each call copies its small tables (twiddles, pair schedule)
+ * (host memory).  The library never allocates device memory (a batch owns
+ * its streams, events and a pinned host table copy) and never frees caller
+ * memory; each call copies its small tables (twiddles, pair schedule)
  * into the caller's workspace, stream-ordered.  A plan is immutable host data
  * and may be shared by several streams if each stream has its own workspace.
  * Calls that overlap on one workspace race.
@@ -166,9 +167,49 @@ int ace_set_profiling(ace_plan *plan, int on);
 int ace_profile_read(ace_plan *plan, double *out_ms, int *out_count);
 
 /* Launch-shape knobs, for the tuner: orbital block of the pair tiles
- * (8 or 16) and the packed transforms per forward/inverse launch
- * (0 = a whole tile).  Changing them changes ace_workspace_bytes. */
-int ace_plan_set_tiling(ace_plan *plan, int block, int chunk);
+ * (8 or 16), the packed transforms per forward/inverse launch (0 = a whole
+ * tile) and the x-pass pencils per workgroup (8, 16 or 32 dividing n; 0 =
+ * the default).  chunk and pencils change no result bit; block changes
+ * which pairs share a transform and the order of the W sums, so results move
+ * by rounding only.  block and chunk change ace_workspace_bytes.
+ * ACE_ERR_ARG for a value outside these sets. */
+int ace_plan_set_tiling(ace_plan *plan, int block, int chunk, int pencils);
+
+/* ---- Batches of independent systems (uneven grids and orbital counts).
+ *
+ * One ace_build per instance (each with its own plan, launch shapes and
+ * optional pair mask), recorded once into a HIP graph whose branches run
+ * instances concurrently, largest first, balanced by estimated work; later
+ * calls with the same pointers replay the recorded graph.  Every instance's
+ * result is bitwise that of a separate ace_build with the same plan and mask.
+ *
+ * ace_batch_create: plans[count] (1 <= count <= ACE_BATCH_MAX) must outlive
+ *   the batch and keep the launch shapes they had at creation (a changed
+ *   shape makes ace_batch_build return ACE_ERR_ARG).  pair_masks may be NULL
+ *   (all pairs everywhere) or hold count host pointers, each NULL or an
+ *   n_orb x n_orb mask as for ace_build; the masks are read here and not kept.
+ * ace_batch_workspace_bytes: device bytes of the one workspace the batch
+ *   slices into per-instance workspaces (256-byte aligned).
+ * ace_batch_build: phi, W, M, xi are host arrays of count device pointers,
+ *   laid out as for ace_build; ex[count] and info[count] are device arrays.
+ *   Outputs of different instances may not overlap each other or any phi.
+ *   The first call on a device creates the batch's streams, events and a
+ *   pinned host copy of the tables; the tables are copied into the workspace
+ *   on `stream` ahead of the work at every call.  flags: 0 replays (or first
+ *   records) the graph, launched on `stream`; ACE_BATCH_EAGER launches the
+ *   same work directly on the branch streams, joined back into `stream`.
+ *   A later call on another device returns ACE_ERR_ARG.
+ * ace_batch_destroy: only after the batch's last build has completed. */
+#define ACE_BATCH_MAX 1024
+#define ACE_BATCH_EAGER 1
+typedef struct ace_batch ace_batch;
+int ace_batch_create(ace_batch **batch, const ace_plan *const *plans,
+                     const uint8_t *const *pair_masks, int count);
+void ace_batch_destroy(ace_batch *batch);
+size_t ace_batch_workspace_bytes(const ace_batch *batch);
+int ace_batch_build(ace_batch *batch, void *stream, void *ws, size_t ws_bytes,
+                    const double *const *phi, double *const *W, double *const *M,
+                    double *const *xi, double *ex, int *info, int flags);
 
 #ifdef __cplusplus
 }

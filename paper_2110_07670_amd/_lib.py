@@ -25,7 +25,10 @@ EXPORTS = ["ace_plan_create", "ace_plan_destroy", "ace_workspace_bytes",
            "ace_apply_workspace_bytes", "ace_build", "ace_apply", "exx_energy",
            "ace_error_string", "ace_last_hip_error", "ace_set_profiling", "ace_profile_read",
            "ace_plan_set_tiling", "ace_overlap_integrals", "ace_wannier", "ace_mlp_screen",
-           "ace_mlp_weight_count"]
+           "ace_mlp_weight_count", "ace_batch_create", "ace_batch_destroy",
+           "ace_batch_workspace_bytes", "ace_batch_build"]
+ACE_BATCH_MAX = 1024
+ACE_BATCH_EAGER = 1
 
 
 class AceError(RuntimeError):
@@ -76,7 +79,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ace_set_profiling.restype = i
     lib.ace_profile_read.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(i)]
     lib.ace_profile_read.restype = i
-    lib.ace_plan_set_tiling.argtypes = [vp, i, i]
+    lib.ace_plan_set_tiling.argtypes = [vp, i, i, i]
     lib.ace_plan_set_tiling.restype = i
     lib.ace_overlap_integrals.argtypes = [vp, vp, vp, sz, vp, vp]
     lib.ace_overlap_integrals.restype = i
@@ -86,6 +89,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ace_mlp_screen.restype = i
     lib.ace_mlp_weight_count.argtypes = []
     lib.ace_mlp_weight_count.restype = i
+    lib.ace_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i]
+    lib.ace_batch_create.restype = i
+    lib.ace_batch_destroy.argtypes = [vp]
+    lib.ace_batch_destroy.restype = None
+    lib.ace_batch_workspace_bytes.argtypes = [vp]
+    lib.ace_batch_workspace_bytes.restype = sz
+    lib.ace_batch_build.argtypes = [vp, vp, vp, sz, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                    ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, i]
+    lib.ace_batch_build.restype = i
     _LIB = lib
     return lib
 
@@ -143,6 +155,7 @@ class Plan:
         self.n, self.cell, self.n_orb, self.alpha = g[0], cl, int(n_orb), float(alpha)
         self.precision = d.precision
         self.npts = g[0] * g[1] * g[2]
+        self.tiling = (16, 0, 0)
 
     @property
     def handle(self):
@@ -159,8 +172,10 @@ class Plan:
     def apply_workspace_bytes(self, n_vec: int) -> int:
         return int(load().ace_apply_workspace_bytes(self._h, int(n_vec)))
 
-    def set_tiling(self, block: int, chunk: int = 0):
-        _check(load().ace_plan_set_tiling(self._h, int(block), int(chunk)), "ace_plan_set_tiling")
+    def set_tiling(self, block: int, chunk: int = 0, pencils: int = 0):
+        _check(load().ace_plan_set_tiling(self._h, int(block), int(chunk), int(pencils)),
+               "ace_plan_set_tiling")
+        self.tiling = (int(block), int(chunk), int(pencils))
 
     def set_profiling(self, on: bool):
         _check(load().ace_set_profiling(self._h, 1 if on else 0), "ace_set_profiling")
@@ -274,3 +289,71 @@ def mlp_screen(plan: Plan, feat, weights, stream=None):
     rc = load().ace_mlp_screen(plan.handle, _stream(stream), _ptr(feat), _ptr(w), _ptr(pred))
     _check(rc, "ace_mlp_screen")
     return pred
+
+
+# ------------------------------------------------------------------ batches
+
+def _ptr_array(items):
+    arr = (ctypes.c_void_p * len(items))()
+    for k, t in enumerate(items):
+        arr[k] = _ptr(t) if t is not None else None
+    return arr
+
+
+class Batch:
+    """Independent systems built together (ace_batch_*): one recorded HIP
+    graph whose branches run the instances concurrently."""
+
+    def __init__(self, plans: Sequence[Plan], pair_masks=None):
+        lib = load()
+        self.plans = list(plans)
+        n = len(self.plans)
+        hs = (ctypes.c_void_p * n)(*[p.handle.value for p in self.plans])
+        masks = None
+        keep = []
+        if pair_masks is not None:
+            masks = (ctypes.c_void_p * n)()
+            for k, (p, m) in enumerate(zip(self.plans, pair_masks)):
+                buf, ptr = _mask_buffer(m, p.n_orb)
+                keep.append(buf)
+                masks[k] = ptr or None
+        h = ctypes.c_void_p()
+        _check(lib.ace_batch_create(ctypes.byref(h), hs, masks, n), "ace_batch_create")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _LIB is not None:
+            _LIB.ace_batch_destroy(self._h)
+            self._h = None
+
+    def workspace_bytes(self) -> int:
+        return int(load().ace_batch_workspace_bytes(self._h))
+
+    def outputs(self, phis):
+        """Fresh W, M, xi lists and ex[count], info[count] for phis."""
+        import torch
+        dev = phis[0].device
+        W = [torch.empty_like(p) for p in phis]
+        xi = [torch.empty_like(p) for p in phis]
+        M = [torch.empty((pl.n_orb, pl.n_orb), dtype=torch.float64, device=dev)
+             for pl in self.plans]
+        ex = torch.zeros((len(phis),), dtype=torch.float64, device=dev)
+        info = torch.zeros((len(phis),), dtype=torch.int32, device=dev)
+        return {"W": W, "M": M, "xi": xi, "ex": ex, "info": info}
+
+    def build_into(self, phis, out, ws, eager: bool = False, stream=None):
+        if len(phis) != len(self.plans):
+            raise ValueError("expected %d orbital sets" % len(self.plans))
+        rc = load().ace_batch_build(self._h, _stream(stream), _ptr(ws),
+                                    ws.numel() * ws.element_size(), _ptr_array(phis),
+                                    _ptr_array(out["W"]), _ptr_array(out["M"]),
+                                    _ptr_array(out["xi"]), _ptr(out["ex"]), _ptr(out["info"]),
+                                    ACE_BATCH_EAGER if eager else 0)
+        _check(rc, "ace_batch_build")
+
+    def build(self, phis, ws=None, eager: bool = False, stream=None):
+        out = self.outputs(phis)
+        if ws is None:
+            ws = workspace(self.workspace_bytes(), phis[0].device)
+        self.build_into(phis, out, ws, eager, stream)
+        return out

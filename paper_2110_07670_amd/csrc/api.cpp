@@ -19,8 +19,11 @@ using acex::Pack;
 namespace {
 
 thread_local int g_last_hip = 0;
+// set while this thread records a graph: stage timing events stay out of it
+thread_local bool g_capturing = false;
 
 constexpr double kTwoPi = 6.28318530717958647692;
+constexpr int kBatchBranches = 4;  // concurrent graph branches of a batch
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -48,6 +51,7 @@ struct ace_plan {
   double omega, dV;
   int block;
   int chunk;
+  int pencils;  // x-pass pencils per workgroup (0: the kernel's default)
   // workspace layout (bytes)
   size_t off_tab, tab_bytes, off_phi32, off_S, off_part, off_L, off_Linv, off_epart, off_epack,
       total;
@@ -59,6 +63,38 @@ struct ace_plan {
   bool profiling = false;
   std::mutex prof_mu;
   std::vector<ProfRec> prof;
+};
+
+namespace {
+struct BuildTables {
+  std::vector<unsigned char> host;  // packs | meta | twiddles | tile orbitals
+  size_t o_packs = 0, o_meta = 0, o_tw = 0, o_orbs = 0, used = 0;
+  std::vector<Tile> tiles;
+  bool masked = false;
+};
+}  // namespace
+
+struct ace_batch {
+  int count = 0;
+  std::vector<const ace_plan*> plans;
+  std::vector<int> shape;             // (block, chunk, pencils) per plan at creation
+  std::vector<BuildTables> tables;
+  std::vector<size_t> ws_off;         // each instance's workspace slice
+  size_t total = 0;
+  std::vector<int> order;             // instances, largest first
+  std::vector<int> branch;            // graph branch of each instance
+  int nbranch = 0;
+  int device = -1;
+  hipStream_t cap = nullptr;          // capture stream
+  std::vector<hipStream_t> streams;   // one per branch
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  unsigned char* pinned = nullptr;    // every instance's tables, back to back
+  std::vector<size_t> pin_off;
+  size_t pin_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key;       // pointers the recorded graph was made for
 };
 
 namespace {
@@ -325,7 +361,7 @@ struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(const ace_plan* plan, int st, hipStream_t strm)
       : p(const_cast<ace_plan*>(plan)), stage(st), s(strm) {
-    if (!p->profiling) return;
+    if (!p->profiling || g_capturing) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
       a = b = nullptr;
       return;
@@ -339,6 +375,150 @@ struct ProfScope {
     p->prof.push_back(ProfRec{stage, a, b});
   }
 };
+
+// ---------------------------------------------------------------- the build sequence
+
+int check_build_args(const ace_plan* p, const void* ws, size_t ws_bytes, const double* phi,
+                     const double* W, const double* M, const double* xi, const double* ex,
+                     const int* info) {
+  if (!p || !ws || !phi || !W || !M || !xi || !ex || !info) return ACE_ERR_ARG;
+  const size_t orb_bytes = (size_t)p->n_orb * p->npts * sizeof(double);
+  if (overlaps(phi, orb_bytes, W, orb_bytes) || overlaps(phi, orb_bytes, xi, orb_bytes) ||
+      overlaps(W, orb_bytes, xi, orb_bytes))
+    return ACE_ERR_ARG;
+  if (ws_bytes < p->total) return ACE_ERR_WORKSPACE;
+  return ACE_OK;
+}
+
+// A0: the pair schedule and the tables the kernels read, built on the host.
+int prepare_tables(const ace_plan* p, const uint8_t* pair_mask, BuildTables& bt) {
+  std::vector<Pack> packs;
+  std::vector<int> meta;
+  std::vector<int> orbs;
+  build_schedule(p, pair_mask, packs, meta, orbs, bt.tiles);
+  bt.masked = pair_mask != nullptr;
+  const size_t bulk = p->prec == 0 ? 8 : 4;
+  bt.o_packs = 0;
+  bt.o_meta = bt.o_packs + align256(std::max<size_t>(packs.size(), 1) * sizeof(Pack));
+  bt.o_tw = bt.o_meta + align256(std::max<size_t>(meta.size(), 1) * sizeof(int));
+  bt.o_orbs = bt.o_tw + align256((size_t)p->n * 2 * bulk);
+  bt.used = bt.o_orbs + align256(std::max<size_t>(orbs.size(), 1) * sizeof(int));
+  if (bt.used > p->tab_bytes) return ACE_ERR_SIZE;
+  bt.host.assign(bt.used, 0);
+  if (!packs.empty())
+    std::memcpy(bt.host.data() + bt.o_packs, packs.data(), packs.size() * sizeof(Pack));
+  if (!meta.empty()) std::memcpy(bt.host.data() + bt.o_meta, meta.data(), meta.size() * sizeof(int));
+  std::memcpy(bt.host.data() + bt.o_tw, p->tw_host.data(), p->tw_host.size());
+  if (!orbs.empty()) std::memcpy(bt.host.data() + bt.o_orbs, orbs.data(), orbs.size() * sizeof(int));
+  return ACE_OK;
+}
+
+// One stream-ordered copy of the tables into the workspace.  The source is
+// pageable host memory, which the runtime stages before the call returns.
+int upload_tables(const ace_plan* p, hipStream_t s, char* w, const BuildTables& bt) {
+  ProfScope ps(p, 7, s);
+  const hipError_t e =
+      hipMemcpyAsync(w + p->off_tab, bt.host.data(), bt.used, hipMemcpyHostToDevice, s);
+  return e == hipSuccess ? ACE_OK : hip_fail(e);
+}
+
+// A1-A10 on stream s, reading tables already resident in the workspace.
+int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
+                  const BuildTables& bt, double* W, double* M, double* xi, double* ex, int* info) {
+  hipError_t e;
+  const int B = p->block;
+  const Pack* d_packs = reinterpret_cast<const Pack*>(w + p->off_tab + bt.o_packs);
+  const int* d_meta = reinterpret_cast<const int*>(w + p->off_tab + bt.o_meta);
+  const int* d_orbs = reinterpret_cast<const int*>(w + p->off_tab + bt.o_orbs);
+
+  acex::GridArgs g;
+  g.n = p->n;
+  g.prec = p->prec;
+  g.npts = p->npts;
+  for (int a = 0; a < 3; ++a) g.g2[a] = (kTwoPi / p->L[a]) * (kTwoPi / p->L[a]);
+  g.kscale = 1.0 / (double)p->npts;
+  g.tw = w + p->off_tab + bt.o_tw;
+  g.cus = device_cus();
+  g.pencils = p->pencils;
+
+  const void* phi_bulk = phi;
+  {
+    ProfScope ps(p, 7, s);
+    if (p->prec == 1) {
+      e = acex::launch_cast_f64_f32(phi, reinterpret_cast<float*>(w + p->off_phi32),
+                                    (int64_t)p->n_orb * p->npts, s);
+      if (e != hipSuccess) return hip_fail(e);
+      phi_bulk = w + p->off_phi32;
+    }
+    e = acex::launch_fill_f64(W, 0.0, (int64_t)p->n_orb * p->npts, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+
+  // ---- A1-A5: pair densities, Poisson solves, W accumulation, tile by tile
+  void* S = w + p->off_S;
+  for (size_t ti = 0; ti < bt.tiles.size(); ++ti) {
+    const Tile& t = bt.tiles[ti];
+    const int chunk = p->chunk > 0 ? p->chunk : t.npack;
+    for (int c0 = 0; c0 < t.npack; c0 += chunk) {
+      const int cnt = std::min(chunk, t.npack - c0);
+      void* Sc = static_cast<char*>(S) + (size_t)c0 * p->s_grid_bytes;
+      {
+        ProfScope ps(p, 0, s);
+        e = acex::launch_fwd_yz(g, phi_bulk, d_packs + t.pack0 + c0, cnt, Sc, s);
+        if (e != hipSuccess) return hip_fail(e);
+      }
+      {
+        ProfScope ps(p, 1, s);
+        e = acex::launch_poisson_x(g, Sc, cnt, s);
+        if (e != hipSuccess) return hip_fail(e);
+      }
+      {
+        ProfScope ps(p, 2, s);
+        e = acex::launch_inv_yz(g, Sc, cnt, s);
+        if (e != hipSuccess) return hip_fail(e);
+      }
+    }
+    {
+      ProfScope ps(p, 3, s);
+      const bool full = !bt.masked && t.bi == B && t.bj == B;
+      e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,
+                                  full ? nullptr : d_meta + t.pack0, t.npack,
+                                  d_orbs + ti * (size_t)2 * B, t.useI, t.useJ, p->alpha, p->npts,
+                                  s);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+  }
+
+  // ---- A6: M = dV Phi^T W
+  double* part = reinterpret_cast<double*>(w + p->off_part);
+  {
+    ProfScope ps(p, 4, s);
+    e = acex::launch_gemm_abt(phi, W, p->n_orb, p->n_orb, p->npts, p->dV, M, part, p->nsplit,
+                              false, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  // ---- A7: -M = L L^T, L^{-1}
+  double* L = reinterpret_cast<double*>(w + p->off_L);
+  double* Linv = reinterpret_cast<double*>(w + p->off_Linv);
+  {
+    ProfScope ps(p, 5, s);
+    e = acex::launch_cholesky_inv(M, p->n_orb, L, Linv, info, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  // ---- A8: xi = W L^{-T}, i.e. xi_k = sum_i Linv[k][i] W_i
+  {
+    ProfScope ps(p, 6, s);
+    e = acex::launch_gemm_ab(Linv, W, p->n_orb, p->n_orb, p->npts, 1.0, xi, info, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  // ---- A10: E_x = tr(M)
+  {
+    ProfScope ps(p, 7, s);
+    e = acex::launch_trace(M, p->n_orb, ex, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return ACE_OK;
+}
 
 }  // namespace
 
@@ -382,6 +562,7 @@ int ace_plan_create(ace_plan** plan, const ace_desc* d) {
   p->dV = p->omega / (double)p->npts;
   p->block = 16;
   p->chunk = 0;
+  p->pencils = 0;
   layout(p);
   make_twiddles(p);
   *plan = p;
@@ -406,12 +587,14 @@ size_t ace_apply_workspace_bytes(const ace_plan* plan, int n_vec) {
          align256((size_t)ns * n_vec * plan->n_orb * sizeof(double));
 }
 
-int ace_plan_set_tiling(ace_plan* plan, int block, int chunk) {
+int ace_plan_set_tiling(ace_plan* plan, int block, int chunk, int pencils) {
   if (!plan) return ACE_ERR_ARG;
   if (block != 8 && block != 16) return ACE_ERR_ARG;
   if (chunk < 0) return ACE_ERR_ARG;
+  if (!acex::pencils_ok(plan->n, pencils)) return ACE_ERR_ARG;
   plan->block = block;
   plan->chunk = chunk;
+  plan->pencils = pencils;
   layout(plan);
   return ACE_OK;
 }
@@ -448,131 +631,16 @@ int ace_profile_read(ace_plan* plan, double* out_ms, int* out_count) {
 
 int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const double* phi,
               const uint8_t* pair_mask, double* W, double* M, double* xi, double* ex, int* info) {
-  if (!p || !ws || !phi || !W || !M || !xi || !ex || !info) return ACE_ERR_ARG;
-  const size_t orb_bytes = (size_t)p->n_orb * p->npts * sizeof(double);
-  if (overlaps(phi, orb_bytes, W, orb_bytes) || overlaps(phi, orb_bytes, xi, orb_bytes) ||
-      overlaps(W, orb_bytes, xi, orb_bytes))
-    return ACE_ERR_ARG;
-  if (ws_bytes < p->total) return ACE_ERR_WORKSPACE;
+  int rc = check_build_args(p, ws, ws_bytes, phi, W, M, xi, ex, info);
+  if (rc != ACE_OK) return rc;
   if (!device_present()) return ACE_ERR_NODEV;
+  BuildTables bt;
+  rc = prepare_tables(p, pair_mask, bt);
+  if (rc != ACE_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  char* w = static_cast<char*>(ws);
-  hipError_t e;
-
-  // ---- A0: pair schedule (host) and tables
-  std::vector<Pack> packs;
-  std::vector<int> meta;
-  std::vector<int> orbs;
-  std::vector<Tile> tiles;
-  build_schedule(p, pair_mask, packs, meta, orbs, tiles);
-  const int B = p->block;
-  const size_t bulk = p->prec == 0 ? 8 : 4;
-  const size_t o_packs = 0;
-  const size_t o_meta = o_packs + align256(std::max<size_t>(packs.size(), 1) * sizeof(Pack));
-  const size_t o_tw = o_meta + align256(std::max<size_t>(meta.size(), 1) * sizeof(int));
-  const size_t o_orbs = o_tw + align256((size_t)p->n * 2 * bulk);
-  const size_t tab_used = o_orbs + align256(std::max<size_t>(orbs.size(), 1) * sizeof(int));
-  if (tab_used > p->tab_bytes) return ACE_ERR_SIZE;
-  std::vector<unsigned char> host(tab_used, 0);
-  if (!packs.empty()) std::memcpy(host.data() + o_packs, packs.data(), packs.size() * sizeof(Pack));
-  if (!meta.empty()) std::memcpy(host.data() + o_meta, meta.data(), meta.size() * sizeof(int));
-  std::memcpy(host.data() + o_tw, p->tw_host.data(), p->tw_host.size());
-  if (!orbs.empty()) std::memcpy(host.data() + o_orbs, orbs.data(), orbs.size() * sizeof(int));
-  {
-    ProfScope ps(p, 7, s);
-    e = hipMemcpyAsync(w + p->off_tab, host.data(), tab_used, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  const Pack* d_packs = reinterpret_cast<const Pack*>(w + p->off_tab + o_packs);
-  const int* d_meta = reinterpret_cast<const int*>(w + p->off_tab + o_meta);
-  const int* d_orbs = reinterpret_cast<const int*>(w + p->off_tab + o_orbs);
-
-  acex::GridArgs g;
-  g.n = p->n;
-  g.prec = p->prec;
-  g.npts = p->npts;
-  for (int a = 0; a < 3; ++a) g.g2[a] = (kTwoPi / p->L[a]) * (kTwoPi / p->L[a]);
-  g.kscale = 1.0 / (double)p->npts;
-  g.tw = w + p->off_tab + o_tw;
-  g.cus = device_cus();
-
-  const void* phi_bulk = phi;
-  {
-    ProfScope ps(p, 7, s);
-    if (p->prec == 1) {
-      e = acex::launch_cast_f64_f32(phi, reinterpret_cast<float*>(w + p->off_phi32),
-                                    (int64_t)p->n_orb * p->npts, s);
-      if (e != hipSuccess) return hip_fail(e);
-      phi_bulk = w + p->off_phi32;
-    }
-    e = acex::launch_fill_f64(W, 0.0, (int64_t)p->n_orb * p->npts, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-
-  // ---- A1-A5: pair densities, Poisson solves, W accumulation, tile by tile
-  void* S = w + p->off_S;
-  for (size_t ti = 0; ti < tiles.size(); ++ti) {
-    const Tile& t = tiles[ti];
-    const int chunk = p->chunk > 0 ? p->chunk : t.npack;
-    for (int c0 = 0; c0 < t.npack; c0 += chunk) {
-      const int cnt = std::min(chunk, t.npack - c0);
-      void* Sc = static_cast<char*>(S) + (size_t)c0 * p->s_grid_bytes;
-      {
-        ProfScope ps(p, 0, s);
-        e = acex::launch_fwd_yz(g, phi_bulk, d_packs + t.pack0 + c0, cnt, Sc, s);
-        if (e != hipSuccess) return hip_fail(e);
-      }
-      {
-        ProfScope ps(p, 1, s);
-        e = acex::launch_poisson_x(g, Sc, cnt, s);
-        if (e != hipSuccess) return hip_fail(e);
-      }
-      {
-        ProfScope ps(p, 2, s);
-        e = acex::launch_inv_yz(g, Sc, cnt, s);
-        if (e != hipSuccess) return hip_fail(e);
-      }
-    }
-    {
-      ProfScope ps(p, 3, s);
-      const bool full = pair_mask == nullptr && t.bi == B && t.bj == B;
-      e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,
-                                  full ? nullptr : d_meta + t.pack0, t.npack,
-                                  d_orbs + ti * (size_t)2 * B, t.useI, t.useJ, p->alpha, p->npts,
-                                  s);
-      if (e != hipSuccess) return hip_fail(e);
-    }
-  }
-
-  // ---- A6: M = dV Phi^T W
-  double* part = reinterpret_cast<double*>(w + p->off_part);
-  {
-    ProfScope ps(p, 4, s);
-    e = acex::launch_gemm_abt(phi, W, p->n_orb, p->n_orb, p->npts, p->dV, M, part, p->nsplit,
-                              false, nullptr, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  // ---- A7: -M = L L^T, L^{-1}
-  double* L = reinterpret_cast<double*>(w + p->off_L);
-  double* Linv = reinterpret_cast<double*>(w + p->off_Linv);
-  {
-    ProfScope ps(p, 5, s);
-    e = acex::launch_cholesky_inv(M, p->n_orb, L, Linv, info, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  // ---- A8: xi = W L^{-T}, i.e. xi_k = sum_i Linv[k][i] W_i
-  {
-    ProfScope ps(p, 6, s);
-    e = acex::launch_gemm_ab(Linv, W, p->n_orb, p->n_orb, p->npts, 1.0, xi, info, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  // ---- A10: E_x = tr(M)
-  {
-    ProfScope ps(p, 7, s);
-    e = acex::launch_trace(M, p->n_orb, ex, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  return ACE_OK;
+  rc = upload_tables(p, s, static_cast<char*>(ws), bt);
+  if (rc != ACE_OK) return rc;
+  return enqueue_build(p, s, static_cast<char*>(ws), phi, bt, W, M, xi, ex, info);
 }
 
 int ace_apply(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const double* xi,
@@ -720,6 +788,200 @@ int ace_mlp_screen(const ace_plan* p, void* stream, const double* feat, const fl
   const hipError_t e = acex::launch_mlp_pairs(feat, p->n_orb, p->L, weights, pred, s);
   if (e != hipSuccess) return hip_fail(e);
   return ACE_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+int ace_batch_create(ace_batch** batch, const ace_plan* const* plans,
+                     const uint8_t* const* pair_masks, int count) {
+  if (!batch || !plans) return ACE_ERR_ARG;
+  *batch = nullptr;
+  if (count < 1 || count > ACE_BATCH_MAX) return ACE_ERR_ARG;
+  for (int k = 0; k < count; ++k)
+    if (!plans[k]) return ACE_ERR_ARG;
+  ace_batch* b = new ace_batch();
+  b->count = count;
+  size_t off = 0, pin = 0;
+  std::vector<double> cost(count);
+  for (int k = 0; k < count; ++k) {
+    const ace_plan* p = plans[k];
+    b->plans.push_back(p);
+    b->shape.insert(b->shape.end(), {p->block, p->chunk, p->pencils});
+    BuildTables bt;
+    const int rc = prepare_tables(p, pair_masks ? pair_masks[k] : nullptr, bt);
+    if (rc != ACE_OK) {
+      delete b;
+      return rc;
+    }
+    int64_t packs = 0;
+    for (const Tile& t : bt.tiles) packs += t.npack;
+    cost[k] = (double)packs * (double)p->npts * std::log2((double)p->npts);
+    b->tables.push_back(std::move(bt));
+    b->ws_off.push_back(off);
+    off += align256(p->total);
+    b->pin_off.push_back(pin);
+    pin += align256(b->tables.back().used);
+  }
+  b->total = off;
+  b->pin_bytes = pin;
+  // largest first, each onto the branch with the least work so far
+  b->order.resize(count);
+  for (int k = 0; k < count; ++k) b->order[k] = k;
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int x, int y) { return cost[x] > cost[y]; });
+  b->nbranch = std::min(count, kBatchBranches);
+  std::vector<double> load(b->nbranch, 0.0);
+  b->branch.assign(count, 0);
+  for (int k : b->order) {
+    const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->branch[k] = j;
+    load[j] += cost[k];
+  }
+  *batch = b;
+  return ACE_OK;
+}
+
+void ace_batch_destroy(ace_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipEvent_t ev : b->join) (void)hipEventDestroy(ev);
+  if (b->pinned) (void)hipHostFree(b->pinned);
+  delete b;
+}
+
+size_t ace_batch_workspace_bytes(const ace_batch* b) { return b ? b->total : 0; }
+
+int ace_batch_build(ace_batch* b, void* stream, void* ws, size_t ws_bytes,
+                    const double* const* phi, double* const* W, double* const* M,
+                    double* const* xi, double* ex, int* info, int flags) {
+  if (!b || !ws || !phi || !W || !M || !xi || !ex || !info) return ACE_ERR_ARG;
+  if (flags & ~ACE_BATCH_EAGER) return ACE_ERR_ARG;
+  if (ws_bytes < b->total) return ACE_ERR_WORKSPACE;
+  char* w = static_cast<char*>(ws);
+  for (int k = 0; k < b->count; ++k) {
+    const ace_plan* p = b->plans[k];
+    if (p->block != b->shape[3 * k] || p->chunk != b->shape[3 * k + 1] ||
+        p->pencils != b->shape[3 * k + 2])
+      return ACE_ERR_ARG;
+    const int rc = check_build_args(p, w + b->ws_off[k], p->total, phi[k], W[k], M[k], xi[k],
+                                    ex + k, info + k);
+    if (rc != ACE_OK) return rc;
+  }
+  // outputs of different instances must not share memory with any input or output
+  for (int k = 0; k < b->count; ++k) {
+    const size_t bk = (size_t)b->plans[k]->n_orb * b->plans[k]->npts * sizeof(double);
+    for (int l = 0; l < b->count; ++l) {
+      if (l == k) continue;
+      const size_t bl = (size_t)b->plans[l]->n_orb * b->plans[l]->npts * sizeof(double);
+      if (overlaps(W[k], bk, W[l], bl) || overlaps(W[k], bk, xi[l], bl) ||
+          overlaps(xi[k], bk, xi[l], bl) || overlaps(W[k], bk, phi[l], bl) ||
+          overlaps(xi[k], bk, phi[l], bl))
+        return ACE_ERR_ARG;
+    }
+  }
+  if (!device_present()) return ACE_ERR_NODEV;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (b->device < 0) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->pinned), std::max<size_t>(b->pin_bytes, 1),
+                      hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e);
+    for (int k = 0; k < b->count; ++k)
+      std::memcpy(b->pinned + b->pin_off[k], b->tables[k].host.data(), b->tables[k].used);
+    if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e);
+    for (int j = 0; j < b->nbranch; ++j) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e);
+      b->streams.push_back(st);
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e);
+      b->join.push_back(ev);
+    }
+    b->device = dev;
+  } else if (dev != b->device) {
+    return ACE_ERR_ARG;
+  }
+  (void)device_cus();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the tables go in ahead of the work, in stream order, from batch-owned pinned memory
+  for (int k = 0; k < b->count; ++k) {
+    e = hipMemcpyAsync(w + b->ws_off[k] + b->plans[k]->off_tab, b->pinned + b->pin_off[k],
+                       b->tables[k].used, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+
+  // fork from `head` onto the branch streams, every instance on its branch, join back
+  auto record = [&](hipStream_t head) -> int {
+    hipError_t er = hipEventRecord(b->fork, head);
+    if (er != hipSuccess) return hip_fail(er);
+    for (hipStream_t st : b->streams)
+      if ((er = hipStreamWaitEvent(st, b->fork, 0)) != hipSuccess) return hip_fail(er);
+    int rc = ACE_OK;
+    for (int k : b->order) {
+      const ace_plan* p = b->plans[k];
+      rc = enqueue_build(p, b->streams[b->branch[k]], w + b->ws_off[k], phi[k], b->tables[k],
+                         W[k], M[k], xi[k], ex + k, info + k);
+      if (rc != ACE_OK) break;
+    }
+    // the join is recorded even after an error, so that a capture always closes
+    for (int j = 0; j < b->nbranch; ++j) {
+      if ((er = hipEventRecord(b->join[j], b->streams[j])) != hipSuccess) return hip_fail(er);
+      if ((er = hipStreamWaitEvent(head, b->join[j], 0)) != hipSuccess) return hip_fail(er);
+    }
+    return rc;
+  };
+
+  if (flags & ACE_BATCH_EAGER) return record(s);
+
+  std::vector<const void*> key;
+  key.reserve(4 * b->count + 3);
+  key.push_back(ws);
+  key.push_back(ex);
+  key.push_back(info);
+  for (int k = 0; k < b->count; ++k) {
+    key.push_back(phi[k]);
+    key.push_back(W[k]);
+    key.push_back(M[k]);
+    key.push_back(xi[k]);
+  }
+  if (!b->exec || key != b->key) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->key.clear();
+    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e);
+    g_capturing = true;
+    const int rc = record(b->cap);
+    g_capturing = false;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(b->cap, &graph);
+    if (rc != ACE_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc != ACE_OK ? rc : hip_fail(e);
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(e);
+    }
+    b->graph = graph;
+    b->exec = exec;
+    b->key = std::move(key);
+  }
+  e = hipGraphLaunch(b->exec, s);
+  return e == hipSuccess ? ACE_OK : hip_fail(e);
 }
 
 }  // extern "C"

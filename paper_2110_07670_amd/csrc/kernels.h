@@ -22,7 +22,11 @@ struct GridArgs {
   double kscale;      // multiplies 4 pi / G^2 (1/N for the Poisson pass, 1 for energy)
   const void* tw;     // n twiddles w_n^k = exp(-2 pi i k / n), bulk precision
   int cus;            // compute units of the device (persistent grids), a multiple of 8
+  int pencils = 0;    // x-pass pencils per workgroup: 8, 16, 32 or 0 (default)
 };
+
+// Is `pencils` a valid x-pass shape for grid n (0 is always valid)?
+bool pencils_ok(int n, int pencils);
 
 // Does one (y, z) plane of the bulk type fit in a workgroup's LDS?
 bool plane_fits(int n, int prec);

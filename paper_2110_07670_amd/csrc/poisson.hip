@@ -67,9 +67,8 @@ constexpr int fwd_threads() {
 template <int N>
 constexpr int line_chunk() { return (N % 16 == 0) ? 16 : 8; }
 
-template <int N>
+template <int N, int C = line_chunk<N>()>
 constexpr int line_threads() {
-  constexpr int C = line_chunk<N>();
   constexpr int N2 = fft_split<N>::N2;
   constexpr int t = C * N2;
   return ((t + 63) / 64) * 64;
@@ -407,12 +406,13 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__(line_threads<N>()) void k_lines(
+template <typename T, int N, int MODE, int C = line_chunk<N>()>
+__global__ __launch_bounds__((line_threads<N, C>())) void k_lines(
     cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts, int64_t estride,
     int64_t ostride, T g0, T g1, T g2, T kscale, double* __restrict__ part) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2;
-  constexpr int C = line_chunk<N>(), NT = line_threads<N>(), NCH = N / C;
+  constexpr int NT = line_threads<N, C>(), NCH = N / C;
+  static_assert(N % C == 0, "pencils per workgroup must divide the grid");
   __shared__ cx<T> lds[N * C];
   __shared__ cx<T> stw[N];
   __shared__ double red[NT / 64 + 1];
@@ -740,14 +740,42 @@ static hipError_t inv_yz_t(const GridArgs& g, void* S, int npack, hipStream_t s)
   return hipGetLastError();
 }
 
-template <typename T, int N, int MODE>
-static hipError_t x_t(const GridArgs& g, void* S, int npack, double* part, hipStream_t s) {
+template <typename T, int N, int MODE, int C>
+static void x_launch(const GridArgs& g, void* S, int npack, double* part, hipStream_t s) {
   const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
-  hipLaunchKernelGGL((k_lines<T, N, MODE>), dim3((N / line_chunk<N>()) * N * npack),
-                     dim3(line_threads<N>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts,
+  hipLaunchKernelGGL((k_lines<T, N, MODE, C>), dim3((N / C) * N * npack),
+                     dim3(line_threads<N, C>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts,
                      (int64_t)N * N, (int64_t)N, T(g.g2[0]), T(g.g2[1]), T(g.g2[2]),
                      T(g.kscale), part);
+}
+
+// The Poisson pass takes its pencils per workgroup from g.pencils (8, 16 or
+// 32 where they divide N; anything else: the default); the energy pass keeps
+// the default, which fixes its partial-sum layout.
+template <typename T, int N, int MODE>
+static hipError_t x_t(const GridArgs& g, void* S, int npack, double* part, hipStream_t s) {
+  if constexpr (MODE == MODE_POISSON) {
+    if constexpr (N % 8 == 0 && line_chunk<N>() != 8) {
+      if (g.pencils == 8) {
+        x_launch<T, N, MODE, 8>(g, S, npack, part, s);
+        return hipGetLastError();
+      }
+    }
+    if constexpr (N % 32 == 0) {
+      if (g.pencils == 32) {
+        x_launch<T, N, MODE, 32>(g, S, npack, part, s);
+        return hipGetLastError();
+      }
+    }
+  }
+  x_launch<T, N, MODE, line_chunk<N>()>(g, S, npack, part, s);
   return hipGetLastError();
+}
+
+bool pencils_ok(int n, int pencils) {
+  if (pencils == 0) return true;
+  if (pencils != 8 && pencils != 16 && pencils != 32) return false;
+  return n % pencils == 0;
 }
 
 hipError_t launch_fwd_yz(const GridArgs& g, const void* phi, const Pack* packs, int npack,
