@@ -327,6 +327,8 @@ def main():
                     help="workload: 2 (default, the headline), 1, 3, 5, or 4 (uneven batch)")
     ap.add_argument("--tune-cache", default=None,
                     help="launch-shape tuner cache for --config 4 (default: user cache)")
+    ap.add_argument("--tiling", default=None,
+                    help="launch shape BLOCK,CHUNK,PENCILS (ace_plan_set_tiling)")
     ap.add_argument("--no-tune", action="store_true",
                     help="--config 4 with the default launch shapes")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
@@ -356,6 +358,8 @@ def main():
     dev = torch.device("cuda:0")
     phi = torch.from_numpy(system.phi).to(dev)
     plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, args.precision, spec.alpha)
+    if args.tiling:
+        plan.set_tiling(*[int(v) for v in args.tiling.split(",")])
     ws = _lib.workspace(plan.workspace_bytes(), dev)
     ws_apply = _lib.workspace(plan.apply_workspace_bytes(spec.n_orb), dev)
     W = torch.empty_like(phi)
@@ -395,7 +399,7 @@ def main():
     value = spec.n_pairs * args.steps / elapsed
     ms_per_step = 1000.0 * elapsed / args.steps
 
-    tiles = tile_plan(spec.n_orb, 16)
+    tiles = tile_plan(spec.n_orb, plan.tiling[0])
     npts = spec.n ** 3
     bulk = 8 if args.precision == "fp64" else 4
     mem_stages = ["yz_fwd", "x_poisson", "yz_inv", "w_accumulate"]
@@ -438,7 +442,8 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32 transforms, f64 W/M/Cholesky/E",
         "data": "synthetic",
         "config": {"workload": workload_text(spec, args.precision),
-                   "n_orb": spec.n_orb, "grid": spec.n, "pairs": spec.n_pairs},
+                   "n_orb": spec.n_orb, "grid": spec.n, "pairs": spec.n_pairs,
+                   "tiling": list(plan.tiling)},
         "roofline": roofline,
         "pair_loop_ms": pair_loop_ms,
         "pair_loop_alg_GBps_32B": spec.n_pairs * 4.0 * bulk * npts / (pair_loop_ms * 1e-3) / 1e9,

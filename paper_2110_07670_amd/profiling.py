@@ -29,8 +29,8 @@ STAGE_OF = [
 
 def stage_of(name: str) -> str:
     if "k_lines" in name:
-        # template argument MODE: 0 Poisson (x), 1 energy, 2 y forward, 3 y inverse
-        mode = name.split("k_lines<")[1].split(">")[0].split(",")[-1].strip()
+        # third template argument MODE: 0 Poisson (x), 1 energy, 2 y forward, 3 y inverse
+        mode = name.split("k_lines<")[1].split(">")[0].split(",")[2].strip()
         return {"0": "x_poisson", "1": "x_energy", "2": "yz_fwd", "3": "yz_inv"}.get(mode, "lines")
     for key, st in STAGE_OF:
         if key in name:
