@@ -24,7 +24,7 @@ STAGE_NAMES = ["yz_fwd", "x_poisson", "yz_inv", "w_accumulate", "m_product", "ch
 EXPORTS = ["ace_plan_create", "ace_plan_destroy", "ace_workspace_bytes",
            "ace_apply_workspace_bytes", "ace_build", "ace_apply", "exx_energy",
            "ace_error_string", "ace_last_hip_error", "ace_set_profiling", "ace_profile_read",
-           "ace_plan_set_tiling", "ace_overlap_integrals", "ace_wannier", "ace_mlp_screen",
+           "ace_plan_set_tiling", "ace_plan_set_schedule", "ace_overlap_integrals", "ace_wannier", "ace_mlp_screen",
            "ace_mlp_weight_count", "ace_batch_create", "ace_batch_destroy",
            "ace_batch_workspace_bytes", "ace_batch_build"]
 ACE_BATCH_MAX = 1024
@@ -81,6 +81,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ace_profile_read.restype = i
     lib.ace_plan_set_tiling.argtypes = [vp, i, i, i]
     lib.ace_plan_set_tiling.restype = i
+    lib.ace_plan_set_schedule.argtypes = [vp, i]
+    lib.ace_plan_set_schedule.restype = i
     lib.ace_overlap_integrals.argtypes = [vp, vp, vp, sz, vp, vp]
     lib.ace_overlap_integrals.restype = i
     lib.ace_wannier.argtypes = [vp, vp, vp, vp, vp]
@@ -156,6 +158,7 @@ class Plan:
         self.precision = d.precision
         self.npts = g[0] * g[1] * g[2]
         self.tiling = (16, 0, 0)
+        self.four_pass = False
 
     @property
     def handle(self):
@@ -176,6 +179,12 @@ class Plan:
         _check(load().ace_plan_set_tiling(self._h, int(block), int(chunk), int(pencils)),
                "ace_plan_set_tiling")
         self.tiling = (int(block), int(chunk), int(pencils))
+
+    def set_schedule(self, four_pass: bool):
+        """Four transform passes everywhere (True) or three where they apply (False)."""
+        _check(load().ace_plan_set_schedule(self._h, 1 if four_pass else 0),
+               "ace_plan_set_schedule")
+        self.four_pass = bool(four_pass)
 
     def set_profiling(self, on: bool):
         _check(load().ace_set_profiling(self._h, 1 if on else 0), "ace_set_profiling")

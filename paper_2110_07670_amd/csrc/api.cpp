@@ -52,6 +52,7 @@ struct ace_plan {
   int block;
   int chunk;
   int pencils;  // x-pass pencils per workgroup (0: the kernel's default)
+  int schedule;  // ACE_SCHEDULE_AUTO or ACE_SCHEDULE_FOUR_PASS
   // workspace layout (bytes)
   size_t off_tab, tab_bytes, off_phi32, off_S, off_part, off_L, off_Linv, off_epart, off_epack,
       total;
@@ -77,7 +78,7 @@ struct BuildTables {
 struct ace_batch {
   int count = 0;
   std::vector<const ace_plan*> plans;
-  std::vector<int> shape;             // (block, chunk, pencils) per plan at creation
+  std::vector<int> shape;             // (block, chunk, pencils, schedule) per plan at creation
   std::vector<BuildTables> tables;
   std::vector<size_t> ws_off;         // each instance's workspace slice
   size_t total = 0;
@@ -454,25 +455,31 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
     if (e != hipSuccess) return hip_fail(e);
   }
 
-  // ---- A1-A5: pair densities, Poisson solves, W accumulation, tile by tile
+  // ---- A1-A5: pair densities, Poisson solves, W accumulation, tile by tile.
+  // Full off-diagonal tiles take three passes where the kernels fit (the
+  // inverse z transform feeds the W update directly); the others take four.
   void* S = w + p->off_S;
+  const bool three_ok =
+      p->schedule == ACE_SCHEDULE_AUTO && !bt.masked && acex::three_pass_ok(p->n, p->prec, B);
   for (size_t ti = 0; ti < bt.tiles.size(); ++ti) {
     const Tile& t = bt.tiles[ti];
+    const bool three = three_ok && !t.diag && t.bi == B && t.bj == B;
+    const int* t_orbs = d_orbs + ti * (size_t)2 * B;
     const int chunk = p->chunk > 0 ? p->chunk : t.npack;
     for (int c0 = 0; c0 < t.npack; c0 += chunk) {
       const int cnt = std::min(chunk, t.npack - c0);
       void* Sc = static_cast<char*>(S) + (size_t)c0 * p->s_grid_bytes;
       {
         ProfScope ps(p, 0, s);
-        e = acex::launch_fwd_yz(g, phi_bulk, d_packs + t.pack0 + c0, cnt, Sc, s);
+        e = acex::launch_fwd_yz(g, phi_bulk, d_packs + t.pack0 + c0, cnt, Sc, s, three);
         if (e != hipSuccess) return hip_fail(e);
       }
       {
         ProfScope ps(p, 1, s);
-        e = acex::launch_poisson_x(g, Sc, cnt, s);
+        e = three ? acex::launch_mid(g, Sc, cnt, s) : acex::launch_poisson_x(g, Sc, cnt, s);
         if (e != hipSuccess) return hip_fail(e);
       }
-      {
+      if (!three) {
         ProfScope ps(p, 2, s);
         e = acex::launch_inv_yz(g, Sc, cnt, s);
         if (e != hipSuccess) return hip_fail(e);
@@ -480,11 +487,14 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
     }
     {
       ProfScope ps(p, 3, s);
-      const bool full = !bt.masked && t.bi == B && t.bj == B;
-      e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,
-                                  full ? nullptr : d_meta + t.pack0, t.npack,
-                                  d_orbs + ti * (size_t)2 * B, t.useI, t.useJ, p->alpha, p->npts,
-                                  s);
+      if (three) {
+        e = acex::launch_zinv_acc(g, B, S, phi, W, t_orbs, p->alpha, s);
+      } else {
+        const bool full = !bt.masked && t.bi == B && t.bj == B;
+        e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,
+                                    full ? nullptr : d_meta + t.pack0, t.npack, t_orbs, t.useI,
+                                    t.useJ, p->alpha, p->npts, s);
+      }
       if (e != hipSuccess) return hip_fail(e);
     }
   }
@@ -563,6 +573,7 @@ int ace_plan_create(ace_plan** plan, const ace_desc* d) {
   p->block = 16;
   p->chunk = 0;
   p->pencils = 0;
+  p->schedule = ACE_SCHEDULE_AUTO;
   layout(p);
   make_twiddles(p);
   *plan = p;
@@ -596,6 +607,13 @@ int ace_plan_set_tiling(ace_plan* plan, int block, int chunk, int pencils) {
   plan->chunk = chunk;
   plan->pencils = pencils;
   layout(plan);
+  return ACE_OK;
+}
+
+int ace_plan_set_schedule(ace_plan* plan, int schedule) {
+  if (!plan) return ACE_ERR_ARG;
+  if (schedule != ACE_SCHEDULE_AUTO && schedule != ACE_SCHEDULE_FOUR_PASS) return ACE_ERR_ARG;
+  plan->schedule = schedule;
   return ACE_OK;
 }
 
@@ -806,7 +824,7 @@ int ace_batch_create(ace_batch** batch, const ace_plan* const* plans,
   for (int k = 0; k < count; ++k) {
     const ace_plan* p = plans[k];
     b->plans.push_back(p);
-    b->shape.insert(b->shape.end(), {p->block, p->chunk, p->pencils});
+    b->shape.insert(b->shape.end(), {p->block, p->chunk, p->pencils, p->schedule});
     BuildTables bt;
     const int rc = prepare_tables(p, pair_masks ? pair_masks[k] : nullptr, bt);
     if (rc != ACE_OK) {
@@ -864,8 +882,8 @@ int ace_batch_build(ace_batch* b, void* stream, void* ws, size_t ws_bytes,
   char* w = static_cast<char*>(ws);
   for (int k = 0; k < b->count; ++k) {
     const ace_plan* p = b->plans[k];
-    if (p->block != b->shape[3 * k] || p->chunk != b->shape[3 * k + 1] ||
-        p->pencils != b->shape[3 * k + 2])
+    if (p->block != b->shape[4 * k] || p->chunk != b->shape[4 * k + 1] ||
+        p->pencils != b->shape[4 * k + 2] || p->schedule != b->shape[4 * k + 3])
       return ACE_ERR_ARG;
     const int rc = check_build_args(p, w + b->ws_off[k], p->total, phi[k], W[k], M[k], xi[k],
                                     ex + k, info + k);

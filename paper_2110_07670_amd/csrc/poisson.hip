@@ -120,7 +120,9 @@ __device__ __forceinline__ void plane_item(int item, int npack, int& x, int& p) 
   x = xcd + 8 * xh;
 }
 
-template <typename T, int N>
+// ZXY: write the result as S[kz][x][ky] (the three-pass schedule, whose middle
+// pass reads one kz plane contiguously) instead of S[x][ky][kz].
+template <typename T, int N, bool ZXY>
 __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
     const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
     cx<T>* __restrict__ S, int npack, int64_t npts) {
@@ -214,17 +216,40 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
     if (next < nitems) fetch(next);
     __builtin_amdgcn_sched_barrier(0);
     lds_barrier();
-    // y step 2 -> global: tasks (pz, k1), pz fastest (coalesced)
-    cx<T>* __restrict__ out = S + (int64_t)p * npts + plane;
+    if constexpr (!ZXY) {
+      // y step 2 -> global: tasks (pz, k1), pz fastest (coalesced)
+      cx<T>* __restrict__ out = S + (int64_t)p * npts + plane;
 #pragma unroll 1
-    for (int task = tid; task < N * N1; task += NT) {
-      const int pz = task % N, k1 = task / N;
-      cx<T> v[N2];
+      for (int task = tid; task < N * N1; task += NT) {
+        const int pz = task % N, k1 = task / N;
+        cx<T> v[N2];
 #pragma unroll
-      for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * P + pz];
-      dft<N2, false>(v);
+        for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * P + pz];
+        dft<N2, false>(v);
 #pragma unroll
-      for (int t = 0; t < N2; ++t) out[(t + N2 * k1) * N + pz] = v[t];
+        for (int t = 0; t < N2; ++t) out[(t + N2 * k1) * N + pz] = v[t];
+      }
+    } else {
+      // y step 2 in place, then the plane leaves transposed: S[kz][x][ky],
+      // consecutive threads on consecutive ky (column reads of the odd-pitch
+      // LDS rows are conflict-free)
+#pragma unroll 1
+      for (int task = tid; task < N * N1; task += NT) {
+        const int pz = task % N, k1 = task / N;
+        cx<T> v[N2];
+#pragma unroll
+        for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * P + pz];
+        dft<N2, false>(v);
+#pragma unroll
+        for (int t = 0; t < N2; ++t) lds[(t + N2 * k1) * P + pz] = v[t];
+      }
+      lds_barrier();
+      cx<T>* __restrict__ out = S + (int64_t)p * npts + (int64_t)x * N;
+#pragma unroll 1
+      for (int e = tid; e < N * N; e += NT) {
+        const int ky = e % N, pz = e / N;
+        out[(int64_t)pz * N * N + ky] = lds[ky * P + pz];
+      }
     }
     lds_barrier();
     item = next;
@@ -289,6 +314,186 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_inv(
     dft<N1, true>(v);
 #pragma unroll
     for (int j1 = 0; j1 < N1; ++j1) io[y * N + t2 + N2 * j1] = v[j1];
+  }
+}
+
+// ------------------------------------------------------------------ three-pass schedule
+// For full off-diagonal tiles where a plane fits LDS the solve takes three
+// passes instead of four:
+//   k_plane_fwd<ZXY> : pair density, y and z transforms, written S[kz][x][ky];
+//   k_plane_mid      : one kz plane [x][ky] (contiguous): forward x, multiply
+//                      by K/N, inverse x, inverse y, written S[kz][x][y];
+//   k_zinv_acc       : inverse z of a tile's transforms at the points
+//                      (x, y0..y0+7, all z), folded straight into W.
+// The potentials never make a round trip through HBM in real space.
+template <typename T, int N>
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
+    cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts, T g0, T g1,
+    T g2, T kscale) {
+  constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
+  constexpr int NT = plane_threads<N>();
+  __shared__ cx<T> lds[N * P];
+  __shared__ cx<T> stw[N];
+  const int bid = blockIdx.x;
+  const int pz = bid % N, p = bid / N;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) stw[i] = tw[i];
+  cx<T>* __restrict__ io = S + (int64_t)p * npts + (int64_t)pz * N * N;
+  const int kz = freq_of_pos<N>(pz);
+  __syncthreads();
+
+  // x forward step 1: tasks (py, t2), py fastest (coalesced rows)
+  for (int task = tid; task < N * N2; task += NT) {
+    const int py = task % N, t2 = task / N;
+    cx<T> v[N1];
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) v[j1] = io[(t2 + N2 * j1) * N + py];
+    dft<N1, false>(v);
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[t2 * k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * P + py] = v[k1];
+  }
+  __syncthreads();
+  // x forward step 2, Coulomb multiply, x inverse step 2: tasks (py, k1)
+  for (int task = tid; task < N * N1; task += NT) {
+    const int py = task % N, k1 = task / N;
+    const int ky = freq_of_pos<N>(py);
+    cx<T> v[N2];
+#pragma unroll
+    for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * P + py];
+    dft<N2, false>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2)
+      v[k2] = scale(v[k2], coulomb_k<T, N>(k1 + N1 * k2, ky, kz, g0, g1, g2, kscale));
+    dft<N2, true>(v);
+#pragma unroll
+    for (int t = 0; t < N2; ++t) lds[(t + N2 * k1) * P + py] = v[t];
+  }
+  __syncthreads();
+  // x inverse step 1 to natural x, in place: tasks (py, t2)
+  for (int task = tid; task < N * N2; task += NT) {
+    const int py = task % N, t2 = task / N;
+    cx<T> v[N1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[(t2 + N2 * k1) * P + py], stw[t2 * k1]);
+    dft<N1, true>(v);
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) lds[(t2 + N2 * j1) * P + py] = v[j1];
+  }
+  __syncthreads();
+  // y inverse step 2 along the rows: tasks (x, k1), x fastest
+  for (int task = tid; task < N * N1; task += NT) {
+    const int x = task % N, k1 = task / N;
+    cx<T> v[N2];
+#pragma unroll
+    for (int t = 0; t < N2; ++t) v[t] = lds[x * P + t + N2 * k1];
+    dft<N2, true>(v);
+#pragma unroll
+    for (int t = 0; t < N2; ++t) lds[x * P + t + N2 * k1] = v[t];
+  }
+  __syncthreads();
+  // y inverse step 1 -> global, natural y: tasks (x, t2), t2 fastest
+  for (int task = tid; task < N * N2; task += NT) {
+    const int t2 = task % N2, x = task / N2;
+    cx<T> v[N1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[x * P + t2 + N2 * k1], stw[t2 * k1]);
+    dft<N1, true>(v);
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) io[x * N + t2 + N2 * j1] = v[j1];
+  }
+}
+
+// Rows of y per inverse-z workgroup (one workgroup: 8 N points).
+constexpr int kZinvRows = 8;
+
+template <int N>
+constexpr int zinv_threads() { return kZinvRows * N; }
+
+template <typename T, int N, int B>
+constexpr bool zinv_ok() {
+  return plane_ok<T, N>() && zinv_threads<N>() <= 1024 &&
+         ((long)(B / 2) * kZinvRows * (N + 1) + N) * (long)sizeof(cx<T>) + 64 <= kLdsBytes;
+}
+
+// A workgroup owns the points (x, y0..y0+7, all z) of a full off-diagonal
+// B x B tile and walks its rows a: the B/2 transforms of row a (pairs (a, 2m)
+// and (a, 2m+1)) are inverse-transformed along z in LDS; then each thread,
+// one point, adds sum_b v_ab phi_b into W_a (once per row) and v_ab phi_a
+// into the W_J sums it keeps in registers until the last row.  Fixed order,
+// no atomics.
+template <typename T, int N, int B>
+__global__ __launch_bounds__(zinv_threads<N>()) void k_zinv_acc(
+    const cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, const double* __restrict__ phi,
+    double* __restrict__ W, const int* __restrict__ orbs, double alpha, int64_t npts) {
+  constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
+  constexpr int NT = zinv_threads<N>(), G = B / 2, YC = kZinvRows;
+  static_assert(B % 2 == 0, "rows of a full tile pack evenly");
+  __shared__ cx<T> lds[G * YC * P];
+  __shared__ cx<T> stw[N];
+  const int tid = threadIdx.x;
+  const int bid = blockIdx.x;
+  const int y0 = (bid % (N / YC)) * YC, x = bid / (N / YC);
+  for (int i = tid; i < N; i += NT) stw[i] = tw[i];
+  // this thread's point for the W update (consecutive threads: consecutive z)
+  const int c = tid / N, z = tid % N;
+  const int64_t r = ((int64_t)x * N + y0 + c) * N + z;
+  const cx<T>* __restrict__ sx = S + (int64_t)x * N + y0;  // + pack*npts + pz*N*N + c
+
+  double phJ[B], accJ[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    phJ[b] = phi[(int64_t)orbs[B + b] * npts + r];
+    accJ[b] = 0.0;
+  }
+  __syncthreads();
+
+#pragma unroll 1
+  for (int a = 0; a < B; ++a) {
+    const int64_t oa = (int64_t)orbs[a] * npts + r;
+    const double phA = phi[oa];
+    const double wA = W[oa];
+    // inverse z step 2 from positions: tasks (c, k1, m), c fastest
+    for (int task = tid; task < YC * N1 * G; task += NT) {
+      const int cc = task % YC, k1 = (task / YC) % N1, m = task / (YC * N1);
+      const cx<T>* __restrict__ src = sx + (int64_t)(a * G + m) * npts + cc;
+      cx<T> v[N2];
+#pragma unroll
+      for (int t = 0; t < N2; ++t) v[t] = src[(int64_t)(t + N2 * k1) * N * N];
+      dft<N2, true>(v);
+#pragma unroll
+      for (int t = 0; t < N2; ++t) lds[(m * YC + cc) * P + t + N2 * k1] = v[t];
+    }
+    lds_barrier();
+    // inverse z step 1 to natural z: tasks (t2, c, m)
+    for (int task = tid; task < YC * N2 * G; task += NT) {
+      const int t2 = task % N2, cc = (task / N2) % YC, m = task / (N2 * YC);
+      cx<T> v[N1];
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1)
+        v[k1] = cmulc(lds[(m * YC + cc) * P + t2 + N2 * k1], stw[t2 * k1]);
+      dft<N1, true>(v);
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) lds[(m * YC + cc) * P + t2 + N2 * j1] = v[j1];
+    }
+    lds_barrier();
+    double accA = 0.0;
+#pragma unroll
+    for (int m = 0; m < G; ++m) {
+      const cx<T> vv = lds[(m * YC + c) * P + z];
+      const double v0 = double(vv.re), v1 = double(vv.im);
+      accA += v0 * phJ[2 * m] + v1 * phJ[2 * m + 1];
+      accJ[2 * m] += v0 * phA;
+      accJ[2 * m + 1] += v1 * phA;
+    }
+    W[oa] = wA - alpha * accA;
+    lds_barrier();
+  }
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int64_t ob = (int64_t)orbs[B + b] * npts + r;
+    W[ob] -= alpha * accJ[b];
   }
 }
 
@@ -705,15 +910,21 @@ int energy_parts_per_pack(int n) {
 
 template <typename T, int N>
 static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs, int npack,
-                           void* S, hipStream_t s) {
+                           void* S, bool zxy, hipStream_t s) {
   const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
   if constexpr (plane_ok<T, N>()) {
     const int items = N * npack;
     const int grid = items < g.cus ? ((items + 7) / 8) * 8 : g.cus;
-    hipLaunchKernelGGL((k_plane_fwd<T, N>), dim3(grid), dim3(fwd_threads<N>()), 0, s,
-                       static_cast<const T*>(phi), packs, tw, static_cast<cx<T>*>(S), npack,
-                       g.npts);
+    if (zxy)
+      hipLaunchKernelGGL((k_plane_fwd<T, N, true>), dim3(grid), dim3(fwd_threads<N>()), 0, s,
+                         static_cast<const T*>(phi), packs, tw, static_cast<cx<T>*>(S), npack,
+                         g.npts);
+    else
+      hipLaunchKernelGGL((k_plane_fwd<T, N, false>), dim3(grid), dim3(fwd_threads<N>()), 0, s,
+                         static_cast<const T*>(phi), packs, tw, static_cast<cx<T>*>(S), npack,
+                         g.npts);
   } else {
+    if (zxy) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_rows_fwd<T, N>), dim3((N * N / kRowsPerBlock) * npack),
                        dim3(row_threads<N>()), 0, s, static_cast<const T*>(phi), packs, tw,
                        static_cast<cx<T>*>(S), npack, g.npts);
@@ -738,6 +949,29 @@ static hipError_t inv_yz_t(const GridArgs& g, void* S, int npack, hipStream_t s)
                        dim3(row_threads<N>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts);
   }
   return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t mid_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
+  if constexpr (plane_ok<T, N>()) {
+    hipLaunchKernelGGL((k_plane_mid<T, N>), dim3(N * npack), dim3(plane_threads<N>()), 0, s,
+                       static_cast<cx<T>*>(S), static_cast<const cx<T>*>(g.tw), npack, g.npts,
+                       T(g.g2[0]), T(g.g2[1]), T(g.g2[2]), T(g.kscale));
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int N, int B>
+static hipError_t zinv_t(const GridArgs& g, const void* S, const double* phi, double* W,
+                         const int* orbs, double alpha, hipStream_t s) {
+  if constexpr (zinv_ok<T, N, B>()) {
+    hipLaunchKernelGGL((k_zinv_acc<T, N, B>), dim3(N * (N / kZinvRows)),
+                       dim3(zinv_threads<N>()), 0, s, static_cast<const cx<T>*>(S),
+                       static_cast<const cx<T>*>(g.tw), phi, W, orbs, alpha, g.npts);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int N, int MODE, int C>
@@ -779,13 +1013,55 @@ bool pencils_ok(int n, int pencils) {
 }
 
 hipError_t launch_fwd_yz(const GridArgs& g, const void* phi, const Pack* packs, int npack,
-                         void* S, hipStream_t s) {
+                         void* S, hipStream_t s, bool zxy) {
   if (npack <= 0) return hipSuccess;
   switch (g.n) {
 #define X(N)                                                                   \
   case N:                                                                      \
-    return g.prec == 0 ? fwd_yz_t<double, N>(g, phi, packs, npack, S, s)       \
-                       : fwd_yz_t<float, N>(g, phi, packs, npack, S, s);
+    return g.prec == 0 ? fwd_yz_t<double, N>(g, phi, packs, npack, S, zxy, s)  \
+                       : fwd_yz_t<float, N>(g, phi, packs, npack, S, zxy, s);
+    ACEX_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool three_pass_ok(int n, int prec, int block) {
+  switch (n) {
+#define X(N)                                                                        \
+  case N:                                                                           \
+    if (block == 16) return prec == 0 ? zinv_ok<double, N, 16>() : zinv_ok<float, N, 16>(); \
+    if (block == 8) return prec == 0 ? zinv_ok<double, N, 8>() : zinv_ok<float, N, 8>();    \
+    return false;
+    ACEX_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
+hipError_t launch_mid(const GridArgs& g, void* S, int npack, hipStream_t s) {
+  if (npack <= 0) return hipSuccess;
+  switch (g.n) {
+#define X(N) \
+  case N: return g.prec == 0 ? mid_t<double, N>(g, S, npack, s) : mid_t<float, N>(g, S, npack, s);
+    ACEX_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_zinv_acc(const GridArgs& g, int block, const void* S, const double* phi,
+                           double* W, const int* orbs, double alpha, hipStream_t s) {
+  switch (g.n) {
+#define X(N)                                                                               \
+  case N:                                                                                  \
+    if (block == 16)                                                                       \
+      return g.prec == 0 ? zinv_t<double, N, 16>(g, S, phi, W, orbs, alpha, s)             \
+                         : zinv_t<float, N, 16>(g, S, phi, W, orbs, alpha, s);             \
+    if (block == 8)                                                                        \
+      return g.prec == 0 ? zinv_t<double, N, 8>(g, S, phi, W, orbs, alpha, s)              \
+                         : zinv_t<float, N, 8>(g, S, phi, W, orbs, alpha, s);              \
+    return hipErrorInvalidValue;
     ACEX_SIZES(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -208,3 +208,13 @@ def test_batch_build_validates_before_device():
     lib.ace_batch_destroy(b)
     for h in hs:
         lib.ace_plan_destroy(h)
+
+
+def test_schedule_knob():
+    lib = _lib.load()
+    rc, h = _create(_desc(n=32, k=8))
+    assert lib.ace_plan_set_schedule(h, 1) == 0
+    assert lib.ace_plan_set_schedule(h, 0) == 0
+    assert lib.ace_plan_set_schedule(h, 2) == _lib.ACE_ERR_ARG
+    assert lib.ace_plan_set_schedule(None, 0) == _lib.ACE_ERR_ARG
+    lib.ace_plan_destroy(h)
