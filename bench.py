@@ -33,45 +33,56 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_water32_n96.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_07670_amd", "csrc", "poisson.hip")
 
 
-def tile_plan(n_orb, block):
-    """(bi, bj, diag, npack) for every tile of the unmasked schedule."""
+def plane_fits(n, bulk):
+    """Does one (y, z) plane (plus twiddles) of the bulk type fit the 160 KiB LDS?"""
+    return (n * (n + 1) + n) * 2 * bulk + 64 <= 163840
+
+
+def three_pass_fits(n, bulk, block):
+    """Do the three-pass kernels fit (plane in LDS, 8 n threads, block/2 z lines x 8)?"""
+    return (plane_fits(n, bulk) and 8 * n <= 1024
+            and ((block // 2) * 8 * (n + 1) + n) * 2 * bulk + 64 <= 163840)
+
+
+def tile_plan(n_orb, block, n=None, bulk=8, four_pass=False):
+    """(bi, bj, diag, npack, three) for every tile of the unmasked schedule;
+    `three`: the tile takes the three-pass schedule (full off-diagonal tile
+    on a grid whose kernels fit)."""
     out = []
     nb = (n_orb + block - 1) // block
+    fits = n is not None and not four_pass and three_pass_fits(n, bulk, block)
     for I in range(nb):
         for J in range(I, nb):
             bi = min(block, n_orb - I * block)
             bj = min(block, n_orb - J * block)
             # two pairs of one row share a transform; a row's odd leftover is alone
             rows = [bi - a for a in range(bi)] if I == J else [bj] * bi
-            out.append((bi, bj, I == J, sum((r + 1) // 2 for r in rows)))
+            three = fits and I != J and bi == block and bj == block
+            out.append((bi, bj, I == J, sum((r + 1) // 2 for r in rows), three))
     return out
-
-
-def plane_fits(n, bulk):
-    """Does one (y, z) plane (plus twiddles) of the bulk type fit the 160 KiB LDS?"""
-    return (n * (n + 1) + n) * 2 * bulk + 64 <= 163840
 
 
 def algorithmic_bytes(stage, tiles, npts, bulk, plane=True):
     """Compulsory HBM bytes of one step's launches of `stage` in this design.
 
     Per packed transform (two pairs) and grid point: yz_fwd writes one
-    complex value; x_poisson reads and writes one; yz_inv reads and writes
-    one; w_accumulate reads one.  Orbital traffic is counted once per tile:
-    yz_fwd reads the tile's orbitals (8 B/pt each); w_accumulate reads them
-    and reads + writes their W rows (24 B/pt each).
+    complex value; x_poisson (the middle pass) reads and writes one; yz_inv
+    (four-pass tiles only) reads and writes one; w_accumulate reads one.
+    Orbital traffic is counted once per tile: yz_fwd reads the tile's
+    orbitals (8 B/pt each); w_accumulate reads them and reads + writes their
+    W rows (24 B/pt each).
     """
     c = 2 * bulk
     # where the plane does not fit, the y/z stage is a row pass plus a column
     # pass: one extra read and write of the complex grid each way
     extra = 0 if plane else 2 * c
     tot = 0
-    for bi, bj, diag, npack in tiles:
+    for bi, bj, diag, npack, three in tiles:
         orbs = bi if diag else bi + bj
         if stage == "yz_fwd":
             tot += (npack * (c + extra) + orbs * 8) * npts
         elif stage == "yz_inv":
-            tot += npack * (2 * c + extra) * npts
+            tot += 0 if three else npack * (2 * c + extra) * npts
         elif stage == "x_poisson":
             tot += npack * 2 * c * npts
         elif stage == "w_accumulate":
@@ -283,7 +294,7 @@ def run_batch(args):
     for p, sp in zip(plans, specs):
         prof = p.profile_read()
         p.set_profiling(False)
-        tiles = tile_plan(sp.n_orb, p.tiling[0])
+        tiles = tile_plan(sp.n_orb, p.tiling[0], sp.n, bulk, p.four_pass)
         for s in mem_stages:
             ms, cnt = prof[s]
             agg[s][0] += ms
@@ -329,6 +340,8 @@ def main():
                     help="launch-shape tuner cache for --config 4 (default: user cache)")
     ap.add_argument("--tiling", default=None,
                     help="launch shape BLOCK,CHUNK,PENCILS (ace_plan_set_tiling)")
+    ap.add_argument("--four-pass", action="store_true",
+                    help="four transform passes on every tile (ace_plan_set_schedule)")
     ap.add_argument("--no-tune", action="store_true",
                     help="--config 4 with the default launch shapes")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
@@ -360,6 +373,8 @@ def main():
     plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, args.precision, spec.alpha)
     if args.tiling:
         plan.set_tiling(*[int(v) for v in args.tiling.split(",")])
+    if args.four_pass:
+        plan.set_schedule(True)
     ws = _lib.workspace(plan.workspace_bytes(), dev)
     ws_apply = _lib.workspace(plan.apply_workspace_bytes(spec.n_orb), dev)
     W = torch.empty_like(phi)
@@ -399,9 +414,9 @@ def main():
     value = spec.n_pairs * args.steps / elapsed
     ms_per_step = 1000.0 * elapsed / args.steps
 
-    tiles = tile_plan(spec.n_orb, plan.tiling[0])
-    npts = spec.n ** 3
     bulk = 8 if args.precision == "fp64" else 4
+    tiles = tile_plan(spec.n_orb, plan.tiling[0], spec.n, bulk, plan.four_pass)
+    npts = spec.n ** 3
     mem_stages = ["yz_fwd", "x_poisson", "yz_inv", "w_accumulate"]
     stages = {}
     for name, (ms, cnt) in prof.items():
