@@ -222,6 +222,40 @@ int ace_batch_build(ace_batch *batch, void *stream, void *ws, size_t ws_bytes,
                     const double *const *phi, double *const *W, double *const *M,
                     double *const *xi, double *ex, int *info, int flags);
 
+/* ---- SCDM localisation (section "s-MTACE Method": a rank-revealing QR of
+ * Psi^* selects columns of the density matrix Gamma = Psi Psi^*, which are
+ * orthonormalised; section "s'-MTACE Method": only grid points with
+ * rho > <rho> and |grad rho| < <|grad rho|> enter the QR).
+ *
+ * Readings (the paper gives no formulas): rho = sum_i phi_i^2; grad rho by
+ * second-order central differences on the periodic grid, compared by its
+ * Euclidean norm; averages over all grid points; the QR is Householder with
+ * Businger-Golub column pivoting (largest residual column norm, the first
+ * on a tie); the selected columns are orthonormalised symmetrically
+ * (Loewdin): phi_loc = U^T Phi with U the orthogonal polar factor of
+ * A_C = Psi^*(:, C), computed by Newton-Schulz iteration.
+ *
+ * scdm_workspace_bytes: device bytes for scdm_preselect (m = 0) or for
+ *   both calls with m kept points.
+ * scdm_preselect: points (device int[n1 n2 n3], caller-owned capacity for
+ *   every grid point) receives the kept flat C-order point indices in
+ *   increasing order, *count (device int) their number.
+ * scdm_localize: the k = n_orb pivoted-QR steps over the m points
+ *   (points NULL: every grid point, m = n1 n2 n3; otherwise m >= n_orb
+ *   device ints); pivots (device int[n_orb]) receives the selected grid
+ *   points in selection order; phi_loc (device, laid out like phi, not
+ *   overlapping it) the localised orbitals, row j localised at pivots[j];
+ *   *info (device int) 0, s + 1 if step s met a zero residual column (the
+ *   orbitals are rank deficient on the points), or n_orb + 1 if the polar
+ *   iteration did not converge (phi_loc is then not orthonormal).
+ * Argument errors as elsewhere (ACE_ERR_ARG for m out of range). */
+size_t scdm_workspace_bytes(const ace_plan *plan, int m);
+int scdm_preselect(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes,
+                   const double *phi, int *points, int *count);
+int scdm_localize(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes,
+                  const double *phi, const int *points, int m, int *pivots,
+                  double *phi_loc, int *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,8 @@ EXPORTS = ["ace_plan_create", "ace_plan_destroy", "ace_workspace_bytes",
            "ace_error_string", "ace_last_hip_error", "ace_set_profiling", "ace_profile_read",
            "ace_plan_set_tiling", "ace_plan_set_schedule", "ace_overlap_integrals", "ace_wannier", "ace_mlp_screen",
            "ace_mlp_weight_count", "ace_batch_create", "ace_batch_destroy",
-           "ace_batch_workspace_bytes", "ace_batch_build"]
+           "ace_batch_workspace_bytes", "ace_batch_build", "scdm_workspace_bytes",
+           "scdm_preselect", "scdm_localize"]
 ACE_BATCH_MAX = 1024
 ACE_BATCH_EAGER = 1
 
@@ -100,6 +101,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ace_batch_build.argtypes = [vp, vp, vp, sz, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, i]
     lib.ace_batch_build.restype = i
+    lib.scdm_workspace_bytes.argtypes = [vp, i]
+    lib.scdm_workspace_bytes.restype = sz
+    lib.scdm_preselect.argtypes = [vp, vp, vp, sz, vp, vp, vp]
+    lib.scdm_preselect.restype = i
+    lib.scdm_localize.argtypes = [vp, vp, vp, sz, vp, vp, i, vp, vp, vp]
+    lib.scdm_localize.restype = i
     _LIB = lib
     return lib
 
@@ -366,3 +373,44 @@ class Batch:
             ws = workspace(self.workspace_bytes(), phis[0].device)
         self.build_into(phis, out, ws, eager, stream)
         return out
+
+
+# ------------------------------------------------------------------ SCDM localisation
+
+def scdm_preselect(plan: Plan, phi, ws=None, stream=None):
+    """Kept grid points of the s' rule (device int32 tensor, increasing)."""
+    import torch
+    if ws is None:
+        ws = workspace(int(load().scdm_workspace_bytes(plan.handle, 0)), phi.device)
+    points = torch.empty((plan.npts,), dtype=torch.int32, device=phi.device)
+    count = torch.zeros((1,), dtype=torch.int32, device=phi.device)
+    rc = load().scdm_preselect(plan.handle, _stream(stream), _ptr(ws),
+                               ws.numel() * ws.element_size(), _ptr(phi), _ptr(points),
+                               _ptr(count))
+    _check(rc, "scdm_preselect")
+    m = int(count.item())
+    return points[:m]
+
+
+def scdm_localize(plan: Plan, phi, points=None, ws=None, stream=None):
+    """(pivots [n_orb] int32, phi_loc like phi, info [1] int32) on the device;
+    points None: every grid point."""
+    import torch
+    m = plan.npts if points is None else int(points.numel())
+    if ws is None:
+        ws = workspace(int(load().scdm_workspace_bytes(plan.handle, m)), phi.device)
+    pivots = torch.empty((plan.n_orb,), dtype=torch.int32, device=phi.device)
+    loc = torch.empty_like(phi)
+    info = torch.zeros((1,), dtype=torch.int32, device=phi.device)
+    rc = load().scdm_localize(plan.handle, _stream(stream), _ptr(ws),
+                              ws.numel() * ws.element_size(), _ptr(phi), _ptr(points), m,
+                              _ptr(pivots), _ptr(loc), _ptr(info))
+    _check(rc, "scdm_localize")
+    return pivots, loc, info
+
+
+def scdm(plan: Plan, phi, preselect: bool = True, stream=None):
+    """SCDM localisation with (default) or without the s' preselection."""
+    pts = scdm_preselect(plan, phi, stream=stream) if preselect else None
+    pivots, loc, info = scdm_localize(plan, phi, pts, stream=stream)
+    return {"points": pts, "pivots": pivots, "phi_loc": loc, "info": info}

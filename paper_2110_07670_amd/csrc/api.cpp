@@ -1003,3 +1003,118 @@ int ace_batch_build(ace_batch* b, void* stream, void* ws, size_t ws_bytes,
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ SCDM localisation
+
+namespace {
+
+struct ScdmLayout {
+  size_t rho, g, part, means, cnt, off, pre_total;
+  size_t A, nrm, perm, v, tau, rdiag, Y, G, Z, partial, state, loc_total;
+  int nsplit;
+};
+
+ScdmLayout scdm_layout(const ace_plan* p, int m) {
+  ScdmLayout l{};
+  const int64_t nb = acex::scdm_sel_blocks(p->npts);
+  size_t o = 0;
+  l.rho = o;
+  o += align256((size_t)p->npts * 8);
+  l.g = o;
+  o += align256((size_t)p->npts * 8);
+  l.part = o;
+  o += align256((size_t)2 * acex::scdm_sum_blocks() * 8);
+  l.means = o;
+  o += align256(16);
+  l.cnt = o;
+  o += align256((size_t)nb * 4);
+  l.off = o;
+  o += align256((size_t)nb * 4);
+  l.pre_total = o;
+  const int k = p->n_orb;
+  l.nsplit = acex::gemm_abt_splits(k, k, k);
+  o = 0;
+  l.A = o;
+  o += align256((size_t)std::max(m, 1) * k * 8);
+  l.nrm = o;
+  o += align256((size_t)std::max(m, 1) * 8);
+  l.perm = o;
+  o += align256((size_t)std::max(m, 1) * 4);
+  l.v = o;
+  o += align256((size_t)k * 8);
+  l.tau = o;
+  o += align256(8);
+  l.rdiag = o;
+  o += align256((size_t)k * 8);
+  l.Y = o;
+  o += align256((size_t)k * k * 8);
+  l.G = o;
+  o += align256((size_t)k * k * 8);
+  l.Z = o;
+  o += align256((size_t)k * k * 8);
+  l.partial = o;
+  o += align256((size_t)l.nsplit * k * k * 8);
+  l.state = o;
+  o += align256(16);
+  l.loc_total = o;
+  return l;
+}
+
+constexpr int kPolarMaxIter = 100;
+
+}  // namespace
+
+extern "C" {
+
+size_t scdm_workspace_bytes(const ace_plan* p, int m) {
+  if (!p || m < 0) return 0;
+  const ScdmLayout l = scdm_layout(p, m);
+  return m > 0 ? std::max(l.pre_total, l.loc_total) : l.pre_total;
+}
+
+int scdm_preselect(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const double* phi,
+                   int* points, int* count) {
+  if (!p || !ws || !phi || !points || !count) return ACE_ERR_ARG;
+  const ScdmLayout l = scdm_layout(p, 0);
+  if (ws_bytes < l.pre_total) return ACE_ERR_WORKSPACE;
+  if (!device_present()) return ACE_ERR_NODEV;
+  char* w = static_cast<char*>(ws);
+  const hipError_t e = acex::launch_scdm_preselect(
+      phi, p->n, p->n_orb, p->L, reinterpret_cast<double*>(w + l.rho),
+      reinterpret_cast<double*>(w + l.g), reinterpret_cast<double*>(w + l.part),
+      reinterpret_cast<double*>(w + l.means), reinterpret_cast<int*>(w + l.cnt),
+      reinterpret_cast<int*>(w + l.off), points, count, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ACE_OK : hip_fail(e);
+}
+
+int scdm_localize(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const double* phi,
+                  const int* points, int m, int* pivots, double* phi_loc, int* info) {
+  if (!p || !ws || !phi || !pivots || !phi_loc || !info) return ACE_ERR_ARG;
+  if (m < p->n_orb || (int64_t)m > p->npts) return ACE_ERR_ARG;
+  if (!points && (int64_t)m != p->npts) return ACE_ERR_ARG;
+  const size_t orb_bytes = (size_t)p->n_orb * p->npts * sizeof(double);
+  if (overlaps(phi, orb_bytes, phi_loc, orb_bytes)) return ACE_ERR_ARG;
+  const ScdmLayout l = scdm_layout(p, m);
+  if (ws_bytes < l.loc_total) return ACE_ERR_WORKSPACE;
+  if (!device_present()) return ACE_ERR_NODEV;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  const int k = p->n_orb;
+  hipError_t e = acex::launch_set_int(info, 0, s);
+  if (e != hipSuccess) return hip_fail(e);
+  e = acex::launch_scdm_qr(phi, points, m, k, p->npts, reinterpret_cast<double*>(w + l.A),
+                           reinterpret_cast<double*>(w + l.nrm), reinterpret_cast<int*>(w + l.perm),
+                           reinterpret_cast<double*>(w + l.v), reinterpret_cast<double*>(w + l.tau),
+                           reinterpret_cast<double*>(w + l.rdiag), pivots, info, s);
+  if (e != hipSuccess) return hip_fail(e);
+  double* Y = reinterpret_cast<double*>(w + l.Y);
+  e = acex::launch_scdm_polar(phi, pivots, k, p->npts, Y, reinterpret_cast<double*>(w + l.G),
+                              reinterpret_cast<double*>(w + l.Z),
+                              reinterpret_cast<double*>(w + l.partial), l.nsplit,
+                              reinterpret_cast<int*>(w + l.state), info, kPolarMaxIter, s);
+  if (e != hipSuccess) return hip_fail(e);
+  e = acex::launch_gemm_ab(Y, phi, k, k, p->npts, 1.0, phi_loc, nullptr, s);
+  return e == hipSuccess ? ACE_OK : hip_fail(e);
+}
+
+}  // extern "C"

@@ -109,4 +109,28 @@ int mlp_weight_count();
 hipError_t launch_mlp_pairs(const double* feat, int n_orb, const double* L, const float* wts,
                             float* pred, hipStream_t s);
 
+// SCDM localisation (scdm.hip).
+// Preselection: rho, g (|grad rho|) npts doubles each; part 2 * scdm_sum_blocks()
+// doubles; means 2 doubles; cnt, off scdm_sel_blocks(npts) ints; points
+// (capacity npts) and *count receive the kept points in increasing order.
+int64_t scdm_sel_blocks(int64_t npts);
+int scdm_sum_blocks();
+hipError_t launch_scdm_preselect(const double* phi, int n, int k, const double* L, double* rho,
+                                 double* g, double* part, double* means, int* cnt, int* off,
+                                 int* points, int* count, hipStream_t s);
+// Pivoted QR of the k x m matrix phi(:, points) (points == nullptr: all m = npts
+// points): A m*k doubles, nrm m doubles, perm m ints, v k doubles, tau 1,
+// rdiag k; pivots[k] = the chosen grid points; info = s + 1 on a zero
+// residual column at step s (must be 0 on entry).
+hipError_t launch_scdm_qr(const double* phi, const int* points, int m, int k, int64_t npts,
+                          double* A, double* nrm, int* perm, double* v, double* tau,
+                          double* rdiag, int* pivots, int* info, hipStream_t s);
+// Newton-Schulz polar factor of A_C^T (A_C = phi at the pivots) into Y (k x k);
+// G, Z k*k doubles, partial nsplit*k*k (nsplit = gemm_abt_splits(k, k, k)),
+// state 3 ints; info = k + 1 if max_iter steps do not converge.
+hipError_t launch_scdm_polar(const double* phi, const int* pivots, int k, int64_t npts, double* Y,
+                             double* G, double* Z, double* partial, int nsplit, int* state,
+                             int* info, int max_iter, hipStream_t s);
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
+
 }  // namespace acex

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     text = open(os.path.join(ROOT, "include", "ace.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b((?:ace|exx)_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:ace|exx|scdm)_[a-z_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_call():
@@ -217,4 +217,26 @@ def test_schedule_knob():
     assert lib.ace_plan_set_schedule(h, 0) == 0
     assert lib.ace_plan_set_schedule(h, 2) == _lib.ACE_ERR_ARG
     assert lib.ace_plan_set_schedule(None, 0) == _lib.ACE_ERR_ARG
+    lib.ace_plan_destroy(h)
+
+
+def test_scdm_validation_before_device():
+    lib = _lib.load()
+    rc, h = _create(_desc(n=16, k=4))
+    pre = lib.scdm_workspace_bytes(h, 0)
+    loc = lib.scdm_workspace_bytes(h, 100)
+    assert pre >= 2 * 16 ** 3 * 8 and loc >= pre
+    assert lib.scdm_workspace_bytes(h, -1) == 0
+    phi, pts, cnt, piv, out, info, ws = (0x10000000 + i * 0x1000000 for i in range(7))
+    assert lib.scdm_preselect(h, None, ws, pre - 1, phi, pts, cnt) == _lib.ACE_ERR_WORKSPACE
+    assert lib.scdm_preselect(h, None, ws, pre, None, pts, cnt) == _lib.ACE_ERR_ARG
+    f = lib.scdm_localize
+    assert f(h, None, ws, loc, phi, pts, 3, piv, out, info) == _lib.ACE_ERR_ARG      # m < n_orb
+    assert f(h, None, ws, loc, phi, None, 100, piv, out, info) == _lib.ACE_ERR_ARG   # all points needs m = N
+    assert f(h, None, ws, loc, phi, pts, 16 ** 3 + 1, piv, out, info) == _lib.ACE_ERR_ARG
+    assert f(h, None, ws, loc, phi, pts, 100, piv, phi + 8, info) == _lib.ACE_ERR_ARG  # overlap
+    assert f(h, None, ws, 1, phi, pts, 100, piv, out, info) == _lib.ACE_ERR_WORKSPACE
+    import torch
+    if torch.cuda.device_count() == 0:
+        assert f(h, None, ws, loc, phi, pts, 100, piv, out, info) == _lib.ACE_ERR_NODEV
     lib.ace_plan_destroy(h)
