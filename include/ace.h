@@ -175,8 +175,8 @@ int ace_profile_read(ace_plan *plan, double *out_ms, int *out_count);
  * ACE_ERR_ARG for a value outside these sets. */
 int ace_plan_set_tiling(ace_plan *plan, int block, int chunk, int pencils);
 
-/* Transform schedule.  ACE_SCHEDULE_AUTO: full off-diagonal pair tiles of
- * an unmasked build take three passes over the scratch grids where the
+/* Transform schedule.  ACE_SCHEDULE_AUTO: full pair tiles (block x block
+ * orbitals) of an unmasked build take three passes over the scratch grids where the
  * grid's plane fits a workgroup's LDS (FP64 n <= 96, FP32 n <= 128): the
  * inverse z transform feeds the W update directly; every other tile takes
  * four passes (inverse y/z written back, then the W update).

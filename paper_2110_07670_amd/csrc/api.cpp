@@ -456,14 +456,14 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
   }
 
   // ---- A1-A5: pair densities, Poisson solves, W accumulation, tile by tile.
-  // Full off-diagonal tiles take three passes where the kernels fit (the
-  // inverse z transform feeds the W update directly); the others take four.
+  // Full tiles take three passes where the kernels fit (the inverse z
+  // transform feeds the W update directly); the others take four.
   void* S = w + p->off_S;
   const bool three_ok =
       p->schedule == ACE_SCHEDULE_AUTO && !bt.masked && acex::three_pass_ok(p->n, p->prec, B);
   for (size_t ti = 0; ti < bt.tiles.size(); ++ti) {
     const Tile& t = bt.tiles[ti];
-    const bool three = three_ok && !t.diag && t.bi == B && t.bj == B;
+    const bool three = three_ok && t.bi == B && t.bj == B;
     const int* t_orbs = d_orbs + ti * (size_t)2 * B;
     const int chunk = p->chunk > 0 ? p->chunk : t.npack;
     for (int c0 = 0; c0 < t.npack; c0 += chunk) {
@@ -488,7 +488,7 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
     {
       ProfScope ps(p, 3, s);
       if (three) {
-        e = acex::launch_zinv_acc(g, B, S, phi, W, t_orbs, p->alpha, s);
+        e = acex::launch_zinv_acc(g, B, t.diag, S, phi, W, t_orbs, p->alpha, s);
       } else {
         const bool full = !bt.masked && t.bi == B && t.bj == B;
         e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,

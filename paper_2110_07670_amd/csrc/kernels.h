@@ -39,15 +39,16 @@ bool supported_n(int n);
 hipError_t launch_fwd_yz(const GridArgs& g, const void* phi, const Pack* packs, int npack,
                          void* S, hipStream_t s, bool zxy = false);
 
-// Three-pass schedule for full off-diagonal tiles (three_pass_ok):
+// Three-pass schedule for full tiles (three_pass_ok):
 // launch_fwd_yz(zxy) -> launch_mid (forward x, K/N, inverse x, inverse y
 // per kz plane, in place) -> launch_zinv_acc (inverse z of the tile's
-// block*block/2 transforms, S + 0 .. npack-1, folded into W of the tile's
-// orbitals orbs[0..2 block)).
+// transforms, S + 0 .. npack-1 in the canonical row order, folded into W of
+// the tile's orbitals orbs[0..2 block)).
 bool three_pass_ok(int n, int prec, int block);
 hipError_t launch_mid(const GridArgs& g, void* S, int npack, hipStream_t s);
-hipError_t launch_zinv_acc(const GridArgs& g, int block, const void* S, const double* phi,
-                           double* W, const int* orbs, double alpha, hipStream_t s);
+hipError_t launch_zinv_acc(const GridArgs& g, int block, bool diag, const void* S,
+                           const double* phi, double* W, const int* orbs, double alpha,
+                           hipStream_t s);
 // x transforms with the Coulomb multiply between forward and inverse, in place.
 hipError_t launch_poisson_x(const GridArgs& g, void* S, int npack, hipStream_t s);
 // x forward transform and sum of K |Z|^2 per workgroup into part[npack][parts_per_pack].

@@ -317,9 +317,22 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_inv(
   }
 }
 
+// Full, unmasked tile: the schedule packs the pairs of each row a two per
+// transform, (a, b) and (a, b + 1), with a row's odd leftover alone, so the
+// pair -> (transform, half) map is known at compile time and each transform
+// is read once as one complex value.
+template <int B, bool DIAG>
+constexpr int row_packs(int a) { return DIAG ? (B - a + 1) / 2 : B / 2; }
+template <int B, bool DIAG>
+constexpr int row_pack0(int a) {
+  int s = 0;
+  for (int r = 0; r < a; ++r) s += row_packs<B, DIAG>(r);
+  return s;
+}
+
 // ------------------------------------------------------------------ three-pass schedule
-// For full off-diagonal tiles where a plane fits LDS the solve takes three
-// passes instead of four:
+// For full tiles where a plane fits LDS the solve takes three passes
+// instead of four:
 //   k_plane_fwd<ZXY> : pair density, y and z transforms, written S[kz][x][ky];
 //   k_plane_mid      : one kz plane [x][ky] (contiguous): forward x, multiply
 //                      by K/N, inverse x, inverse y, written S[kz][x][y];
@@ -417,13 +430,13 @@ constexpr bool zinv_ok() {
          ((long)(B / 2) * kZinvRows * (N + 1) + N) * (long)sizeof(cx<T>) + 64 <= kLdsBytes;
 }
 
-// A workgroup owns the points (x, y0..y0+7, all z) of a full off-diagonal
-// B x B tile and walks its rows a: the B/2 transforms of row a (pairs (a, 2m)
-// and (a, 2m+1)) are inverse-transformed along z in LDS; then each thread,
-// one point, adds sum_b v_ab phi_b into W_a (once per row) and v_ab phi_a
-// into the W_J sums it keeps in registers until the last row.  Fixed order,
-// no atomics.
-template <typename T, int N, int B>
+// A workgroup owns the points (x, y0..y0+7, all z) of a full B x B tile and
+// walks its rows a: the transforms of row a (pairs (a, b0) and (a, b0 + 1))
+// are inverse-transformed along z in LDS; then each thread, one point, folds
+// them into the W sums it keeps in registers.  Off-diagonal tiles: W_a is
+// updated once per row (sum_b v_ab phi_b) and the B sums of W_J at the end;
+// diagonal tiles: all B sums at the end.  Fixed order, no atomics.
+template <typename T, int N, int B, bool DIAG>
 __global__ __launch_bounds__(zinv_threads<N>()) void k_zinv_acc(
     const cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, const double* __restrict__ phi,
     double* __restrict__ W, const int* __restrict__ orbs, double alpha, int64_t npts) {
@@ -441,23 +454,29 @@ __global__ __launch_bounds__(zinv_threads<N>()) void k_zinv_acc(
   const int64_t r = ((int64_t)x * N + y0 + c) * N + z;
   const cx<T>* __restrict__ sx = S + (int64_t)x * N + y0;  // + pack*npts + pz*N*N + c
 
-  double phJ[B], accJ[B];
+  // off-diagonal: ph = phi_J, acc = W_J sums; diagonal: the tile's B orbitals
+  double ph[B], acc[B];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    phJ[b] = phi[(int64_t)orbs[B + b] * npts + r];
-    accJ[b] = 0.0;
+    ph[b] = phi[(int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r];
+    acc[b] = 0.0;
   }
   __syncthreads();
 
+  int q0 = 0;  // first transform of row a
 #pragma unroll 1
   for (int a = 0; a < B; ++a) {
+    const int ga = DIAG ? (B - a + 1) / 2 : G;  // transforms in row a
     const int64_t oa = (int64_t)orbs[a] * npts + r;
-    const double phA = phi[oa];
-    const double wA = W[oa];
+    double phA = 0.0, wA = 0.0;
+    if constexpr (!DIAG) {
+      phA = phi[oa];
+      wA = W[oa];
+    }
     // inverse z step 2 from positions: tasks (c, k1, m), c fastest
-    for (int task = tid; task < YC * N1 * G; task += NT) {
+    for (int task = tid; task < YC * N1 * ga; task += NT) {
       const int cc = task % YC, k1 = (task / YC) % N1, m = task / (YC * N1);
-      const cx<T>* __restrict__ src = sx + (int64_t)(a * G + m) * npts + cc;
+      const cx<T>* __restrict__ src = sx + (int64_t)(q0 + m) * npts + cc;
       cx<T> v[N2];
 #pragma unroll
       for (int t = 0; t < N2; ++t) v[t] = src[(int64_t)(t + N2 * k1) * N * N];
@@ -467,7 +486,7 @@ __global__ __launch_bounds__(zinv_threads<N>()) void k_zinv_acc(
     }
     lds_barrier();
     // inverse z step 1 to natural z: tasks (t2, c, m)
-    for (int task = tid; task < YC * N2 * G; task += NT) {
+    for (int task = tid; task < YC * N2 * ga; task += NT) {
       const int t2 = task % N2, cc = (task / N2) % YC, m = task / (N2 * YC);
       cx<T> v[N1];
 #pragma unroll
@@ -478,22 +497,44 @@ __global__ __launch_bounds__(zinv_threads<N>()) void k_zinv_acc(
       for (int j1 = 0; j1 < N1; ++j1) lds[(m * YC + cc) * P + t2 + N2 * j1] = v[j1];
     }
     lds_barrier();
-    double accA = 0.0;
+    if constexpr (!DIAG) {
+      double accA = 0.0;
 #pragma unroll
-    for (int m = 0; m < G; ++m) {
-      const cx<T> vv = lds[(m * YC + c) * P + z];
-      const double v0 = double(vv.re), v1 = double(vv.im);
-      accA += v0 * phJ[2 * m] + v1 * phJ[2 * m + 1];
-      accJ[2 * m] += v0 * phA;
-      accJ[2 * m + 1] += v1 * phA;
+      for (int m = 0; m < G; ++m) {
+        const cx<T> vv = lds[(m * YC + c) * P + z];
+        const double v0 = double(vv.re), v1 = double(vv.im);
+        accA += v0 * ph[2 * m] + v1 * ph[2 * m + 1];
+        acc[2 * m] += v0 * phA;
+        acc[2 * m + 1] += v1 * phA;
+      }
+      W[oa] = wA - alpha * accA;
+    } else {
+      // row a at compile time, so every register index is static
+      sfor<0, B>([&](auto ac) {
+        constexpr int ar = decltype(ac)::value;
+        if (a == ar) {
+          sfor<0, row_packs<B, true>(ar)>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            constexpr int b0 = ar + 2 * m;
+            const cx<T> vv = lds[(m * YC + c) * P + z];
+            const double v0 = double(vv.re), v1 = double(vv.im);
+            acc[ar] += v0 * ph[b0];
+            if constexpr (b0 != ar) acc[b0] += v0 * ph[ar];
+            if constexpr (b0 + 1 < B) {
+              acc[ar] += v1 * ph[b0 + 1];
+              acc[b0 + 1] += v1 * ph[ar];
+            }
+          });
+        }
+      });
     }
-    W[oa] = wA - alpha * accA;
+    q0 += ga;
     lds_barrier();
   }
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    const int64_t ob = (int64_t)orbs[B + b] * npts + r;
-    W[ob] -= alpha * accJ[b];
+    const int64_t ob = (int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r;
+    W[ob] -= alpha * acc[b];
   }
 }
 
@@ -782,19 +823,6 @@ __global__ __launch_bounds__(256) void k_accumulate(
   }
 }
 
-// Full, unmasked tile: the schedule packs the pairs of each row a two per
-// transform, (a, b) and (a, b + 1), with a row's odd leftover alone, so the
-// pair -> (transform, half) map is known at compile time and each transform
-// is read once as one complex value.
-template <int B, bool DIAG>
-constexpr int row_packs(int a) { return DIAG ? (B - a + 1) / 2 : B / 2; }
-template <int B, bool DIAG>
-constexpr int row_pack0(int a) {
-  int s = 0;
-  for (int r = 0; r < a; ++r) s += row_packs<B, DIAG>(r);
-  return s;
-}
-
 template <typename TS, int B, bool DIAG>
 __global__ __launch_bounds__(256) void k_accumulate_full(
     const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W,
@@ -963,12 +991,17 @@ static hipError_t mid_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
 }
 
 template <typename T, int N, int B>
-static hipError_t zinv_t(const GridArgs& g, const void* S, const double* phi, double* W,
-                         const int* orbs, double alpha, hipStream_t s) {
+static hipError_t zinv_t(const GridArgs& g, bool diag, const void* S, const double* phi,
+                         double* W, const int* orbs, double alpha, hipStream_t s) {
   if constexpr (zinv_ok<T, N, B>()) {
-    hipLaunchKernelGGL((k_zinv_acc<T, N, B>), dim3(N * (N / kZinvRows)),
-                       dim3(zinv_threads<N>()), 0, s, static_cast<const cx<T>*>(S),
-                       static_cast<const cx<T>*>(g.tw), phi, W, orbs, alpha, g.npts);
+    if (diag)
+      hipLaunchKernelGGL((k_zinv_acc<T, N, B, true>), dim3(N * (N / kZinvRows)),
+                         dim3(zinv_threads<N>()), 0, s, static_cast<const cx<T>*>(S),
+                         static_cast<const cx<T>*>(g.tw), phi, W, orbs, alpha, g.npts);
+    else
+      hipLaunchKernelGGL((k_zinv_acc<T, N, B, false>), dim3(N * (N / kZinvRows)),
+                         dim3(zinv_threads<N>()), 0, s, static_cast<const cx<T>*>(S),
+                         static_cast<const cx<T>*>(g.tw), phi, W, orbs, alpha, g.npts);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
@@ -1050,17 +1083,18 @@ hipError_t launch_mid(const GridArgs& g, void* S, int npack, hipStream_t s) {
   }
 }
 
-hipError_t launch_zinv_acc(const GridArgs& g, int block, const void* S, const double* phi,
-                           double* W, const int* orbs, double alpha, hipStream_t s) {
+hipError_t launch_zinv_acc(const GridArgs& g, int block, bool diag, const void* S,
+                           const double* phi, double* W, const int* orbs, double alpha,
+                           hipStream_t s) {
   switch (g.n) {
 #define X(N)                                                                               \
   case N:                                                                                  \
     if (block == 16)                                                                       \
-      return g.prec == 0 ? zinv_t<double, N, 16>(g, S, phi, W, orbs, alpha, s)             \
-                         : zinv_t<float, N, 16>(g, S, phi, W, orbs, alpha, s);             \
+      return g.prec == 0 ? zinv_t<double, N, 16>(g, diag, S, phi, W, orbs, alpha, s)       \
+                         : zinv_t<float, N, 16>(g, diag, S, phi, W, orbs, alpha, s);       \
     if (block == 8)                                                                        \
-      return g.prec == 0 ? zinv_t<double, N, 8>(g, S, phi, W, orbs, alpha, s)              \
-                         : zinv_t<float, N, 8>(g, S, phi, W, orbs, alpha, s);              \
+      return g.prec == 0 ? zinv_t<double, N, 8>(g, diag, S, phi, W, orbs, alpha, s)        \
+                         : zinv_t<float, N, 8>(g, diag, S, phi, W, orbs, alpha, s);        \
     return hipErrorInvalidValue;
     ACEX_SIZES(X)
 #undef X
