@@ -56,6 +56,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _LIB
     if not os.path.exists(path):
         raise RuntimeError("libacex.so is not built (%s); run __graft_entry__.build()" % path)
+    # torch first: the library must bind to the HIP runtime torch has loaded,
+    # or the process ends up with two runtimes that do not share devices
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, sz, i, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
     lib.ace_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(AceDesc)]
