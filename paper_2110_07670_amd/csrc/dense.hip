@@ -25,7 +25,7 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
 // 64 x 64 = 4 x 4 MFMA blocks.  K staged through LDS in slabs of KT; the next
 // slab is loaded into registers while the current one feeds the MFMAs.
 constexpr int kAbtTile = 128;
-constexpr int kAbtKT = 16;
+constexpr int kAbtKT = 32;
 constexpr int kAbtPitch = kAbtKT + 1;
 constexpr int kAbtPer = kAbtTile * kAbtKT / 256;  // elements per thread per operand
 
