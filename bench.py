@@ -391,7 +391,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=192)
+    ap.add_argument("--cpu-pairs", type=int, default=640)
     ap.add_argument("--config", type=int, default=2,
                     help="workload: 2 (default, the headline), 1, 3, 5, or 4 (uneven batch)")
     ap.add_argument("--tune-cache", default=None,
