@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 from oracle import ace_oracle as O  # noqa: E402
 from paper_2110_07670_amd import synth  # noqa: E402
 
-SAMPLE_ROWS = {3: [0, 77, 200], 5: [0, 255, 511]}
+SAMPLE_ROWS = {2: [0, 63, 127], 3: [0, 77, 200], 5: [0, 255, 511]}
 _S = {}
 
 
