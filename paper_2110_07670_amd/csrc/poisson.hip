@@ -135,7 +135,7 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
   const int tid = threadIdx.x;
   const int t2 = tid % N2;
   const int nitems = N * npack;
-  for (int i = tid; i < N; i += NT) stw[i] = tw[i];
+  for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];  // stw[k1 N2 + t2] = w^(t2 k1)
   __syncthreads();
 
   // phi_a, phi_b, phi_d of one item at this thread's z-step-1 elements
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
           v[j1] = {fa[q][j1] * fb[q][j1], fa[q][j1] * (dmask * fd[q][j1])};
         dft<N1, false>(v);
 #pragma unroll
-        for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[t2 * k1]);
+        for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[k1 * N2 + t2]);
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) lds[y * P + t2 + N2 * k1] = v[k1];
       }
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
       for (int j1 = 0; j1 < N1; ++j1) v[j1] = lds[(t2 + N2 * j1) * P + pz];
       dft<N1, false>(v);
 #pragma unroll
-      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[t2 * k1]);
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[k1 * N2 + t2]);
 #pragma unroll
       for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * P + pz] = v[k1];
     }
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
   const int bid = blockIdx.x;
   const int pz = bid % N, p = bid / N;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) stw[i] = tw[i];
+  for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];  // stw[k1 N2 + t2] = w^(t2 k1)
   cx<T>* __restrict__ io = S + (int64_t)p * npts + (int64_t)pz * N * N;
   const int kz = freq_of_pos<N>(pz);
   __syncthreads();
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
     for (int j1 = 0; j1 < N1; ++j1) v[j1] = io[(t2 + N2 * j1) * N + py];
     dft<N1, false>(v);
 #pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[t2 * k1]);
+    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[k1 * N2 + t2]);
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * P + py] = v[k1];
   }
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
     const int py = task % N, t2 = task / N;
     cx<T> v[N1];
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[(t2 + N2 * k1) * P + py], stw[t2 * k1]);
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[(t2 + N2 * k1) * P + py], stw[k1 * N2 + t2]);
     dft<N1, true>(v);
 #pragma unroll
     for (int j1 = 0; j1 < N1; ++j1) lds[(t2 + N2 * j1) * P + py] = v[j1];
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
     const int t2 = task % N2, x = task / N2;
     cx<T> v[N1];
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[x * P + t2 + N2 * k1], stw[t2 * k1]);
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[x * P + t2 + N2 * k1], stw[k1 * N2 + t2]);
     dft<N1, true>(v);
 #pragma unroll
     for (int j1 = 0; j1 < N1; ++j1) io[x * N + t2 + N2 * j1] = v[j1];
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(zinv_threads<N>()) void k_zinv_acc(
   const int tid = threadIdx.x;
   const int bid = blockIdx.x;
   const int y0 = (bid % (N / YC)) * YC, x = bid / (N / YC);
-  for (int i = tid; i < N; i += NT) stw[i] = tw[i];
+  for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];  // stw[k1 N2 + t2] = w^(t2 k1)
   // this thread's point for the W update (consecutive threads: consecutive z)
   const int c = tid / N, z = tid % N;
   const int64_t r = ((int64_t)x * N + y0 + c) * N + z;
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(zinv_threads<N>()) void k_zinv_acc(
       cx<T> v[N1];
 #pragma unroll
       for (int k1 = 0; k1 < N1; ++k1)
-        v[k1] = cmulc(lds[(m * YC + cc) * P + t2 + N2 * k1], stw[t2 * k1]);
+        v[k1] = cmulc(lds[(m * YC + cc) * P + t2 + N2 * k1], stw[k1 * N2 + t2]);
       dft<N1, true>(v);
 #pragma unroll
       for (int j1 = 0; j1 < N1; ++j1) lds[(m * YC + cc) * P + t2 + N2 * j1] = v[j1];
@@ -667,7 +667,7 @@ __global__ __launch_bounds__((line_threads<N, C>())) void k_lines(
   const int outer = (bid / NCH) % N;
   const int p = bid / (NCH * N);
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) stw[i] = tw[i];
+  for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];  // stw[k1 N2 + t2] = w^(t2 k1)
   cx<T>* __restrict__ base = S + (int64_t)p * npts + (int64_t)outer * ostride + chunk * C;
   __syncthreads();
 
@@ -680,7 +680,7 @@ __global__ __launch_bounds__((line_threads<N, C>())) void k_lines(
       for (int j1 = 0; j1 < N1; ++j1) v[j1] = base[(int64_t)(t2 + N2 * j1) * estride + c];
       dft<N1, false>(v);
 #pragma unroll
-      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[t2 * k1]);
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[k1 * N2 + t2]);
 #pragma unroll
       for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * C + c] = v[k1];
     }
@@ -740,7 +740,7 @@ __global__ __launch_bounds__((line_threads<N, C>())) void k_lines(
     const int c = task % C, t2 = task / C;
     cx<T> v[N1];
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[(t2 + N2 * k1) * C + c], stw[t2 * k1]);
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[(t2 + N2 * k1) * C + c], stw[k1 * N2 + t2]);
     dft<N1, true>(v);
 #pragma unroll
     for (int j1 = 0; j1 < N1; ++j1) base[(int64_t)(t2 + N2 * j1) * estride + c] = v[j1];
