@@ -39,9 +39,11 @@ def plane_fits(n, bulk):
 
 
 def three_pass_fits(n, bulk, block):
-    """Do the three-pass kernels fit (plane in LDS, 8 n threads, block/2 z lines x 8)?"""
-    return (plane_fits(n, bulk) and 8 * n <= 1024
-            and ((block // 2) * 8 * (n + 1) + n) * 2 * bulk + 64 <= 163840)
+    """Do the three-pass kernels fit (plane in LDS; 8 n threads and
+    block/2 x 8 z lines in the last pass)?"""
+    rows = 8
+    return (plane_fits(n, bulk) and rows * n <= 1024
+            and ((block // 2) * rows * (n + 1) + n) * 2 * bulk + 64 <= 163840)
 
 
 def tile_plan(n_orb, block, n=None, bulk=8, four_pass=False):

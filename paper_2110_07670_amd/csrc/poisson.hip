@@ -418,30 +418,33 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
   }
 }
 
-// Rows of y per inverse-z workgroup (one workgroup: 8 N points).
-constexpr int kZinvRows = 8;
+// Rows of y per inverse-z workgroup (one workgroup: rows x N points).  Eight
+// rows read 128 B (FP64) of each scratch row per transform; four rows (64 B
+// segments, two workgroups per CU) measured slower.
+template <typename T>
+constexpr int zinv_rows() { return 8; }
 
-template <int N>
-constexpr int zinv_threads() { return kZinvRows * N; }
+template <typename T, int N>
+constexpr int zinv_threads() { return zinv_rows<T>() * N; }
 
 template <typename T, int N, int B>
 constexpr bool zinv_ok() {
-  return plane_ok<T, N>() && zinv_threads<N>() <= 1024 &&
-         ((long)(B / 2) * kZinvRows * (N + 1) + N) * (long)sizeof(cx<T>) + 64 <= kLdsBytes;
+  return plane_ok<T, N>() && zinv_threads<T, N>() <= 1024 &&
+         ((long)(B / 2) * zinv_rows<T>() * (N + 1) + N) * (long)sizeof(cx<T>) + 64 <= kLdsBytes;
 }
 
-// A workgroup owns the points (x, y0..y0+7, all z) of a full B x B tile and
+// A workgroup owns the points (x, y0 .. y0 + YC - 1, all z) of a full B x B tile and
 // walks its rows a: the transforms of row a (pairs (a, b0) and (a, b0 + 1))
 // are inverse-transformed along z in LDS; then each thread, one point, folds
 // them into the W sums it keeps in registers.  Off-diagonal tiles: W_a is
 // updated once per row (sum_b v_ab phi_b) and the B sums of W_J at the end;
 // diagonal tiles: all B sums at the end.  Fixed order, no atomics.
 template <typename T, int N, int B, bool DIAG>
-__global__ __launch_bounds__(zinv_threads<N>()) void k_zinv_acc(
+__global__ __launch_bounds__((zinv_threads<T, N>())) void k_zinv_acc(
     const cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, const double* __restrict__ phi,
     double* __restrict__ W, const int* __restrict__ orbs, double alpha, int64_t npts) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
-  constexpr int NT = zinv_threads<N>(), G = B / 2, YC = kZinvRows;
+  constexpr int NT = zinv_threads<T, N>(), G = B / 2, YC = zinv_rows<T>();
   static_assert(B % 2 == 0, "rows of a full tile pack evenly");
   __shared__ cx<T> lds[G * YC * P];
   __shared__ cx<T> stw[N];
@@ -995,12 +998,12 @@ static hipError_t zinv_t(const GridArgs& g, bool diag, const void* S, const doub
                          double* W, const int* orbs, double alpha, hipStream_t s) {
   if constexpr (zinv_ok<T, N, B>()) {
     if (diag)
-      hipLaunchKernelGGL((k_zinv_acc<T, N, B, true>), dim3(N * (N / kZinvRows)),
-                         dim3(zinv_threads<N>()), 0, s, static_cast<const cx<T>*>(S),
+      hipLaunchKernelGGL((k_zinv_acc<T, N, B, true>), dim3(N * (N / zinv_rows<T>())),
+                         dim3(zinv_threads<T, N>()), 0, s, static_cast<const cx<T>*>(S),
                          static_cast<const cx<T>*>(g.tw), phi, W, orbs, alpha, g.npts);
     else
-      hipLaunchKernelGGL((k_zinv_acc<T, N, B, false>), dim3(N * (N / kZinvRows)),
-                         dim3(zinv_threads<N>()), 0, s, static_cast<const cx<T>*>(S),
+      hipLaunchKernelGGL((k_zinv_acc<T, N, B, false>), dim3(N * (N / zinv_rows<T>())),
+                         dim3(zinv_threads<T, N>()), 0, s, static_cast<const cx<T>*>(S),
                          static_cast<const cx<T>*>(g.tw), phi, W, orbs, alpha, g.npts);
     return hipGetLastError();
   }
