@@ -466,6 +466,33 @@ __global__ __launch_bounds__((zinv_threads<T, N>())) void k_zinv_acc(
   }
   __syncthreads();
 
+  // inverse z step 2, tasks (c, k1, m) with c fastest, Q2 per thread.  With
+  // FP32 transforms the loads of row a + 1 are issued before row a's W update
+  // so that they are in flight while it runs (the barriers order LDS only);
+  // with FP64 ones the registers for that do not fit next to the W sums
+  // (measured slower with the spills) and each row loads at its start.  With
+  // the prefetch the four-step twiddles are applied at the end of step 2,
+  // which keeps step 1 light; without it, at the start of step 1.
+  constexpr int T2MAX = YC * N1 * G;
+  // every thread has exactly one step-2 task in every row: no bounds test
+  constexpr bool EXACT = !DIAG && T2MAX == NT;
+  constexpr bool PF = sizeof(T) == 4;
+  constexpr int Q2 = PF ? (T2MAX + NT - 1) / NT : 1;
+  cx<T> pre[Q2][N2];
+  auto fetch = [&](int q0n, int gan) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < Q2; ++q) {
+      const int task = tid + q * NT;
+      if (EXACT || task < YC * N1 * gan) {
+        const int cc = task % YC, k1 = (task / YC) % N1, m = task / (YC * N1);
+        const cx<T>* __restrict__ src = sx + (int64_t)(q0n + m) * npts + cc;
+#pragma unroll
+        for (int t = 0; t < N2; ++t) pre[q][t] = src[(int64_t)(t + N2 * k1) * N * N];
+      }
+    }
+  };
+  if constexpr (PF) fetch(0, DIAG ? (B + 1) / 2 : G);
+
   int q0 = 0;  // first transform of row a
 #pragma unroll 1
   for (int a = 0; a < B; ++a) {
@@ -476,16 +503,30 @@ __global__ __launch_bounds__((zinv_threads<T, N>())) void k_zinv_acc(
       phA = phi[oa];
       wA = W[oa];
     }
-    // inverse z step 2 from positions: tasks (c, k1, m), c fastest
-    for (int task = tid; task < YC * N1 * ga; task += NT) {
-      const int cc = task % YC, k1 = (task / YC) % N1, m = task / (YC * N1);
-      const cx<T>* __restrict__ src = sx + (int64_t)(q0 + m) * npts + cc;
-      cx<T> v[N2];
+    if constexpr (PF) {
 #pragma unroll
-      for (int t = 0; t < N2; ++t) v[t] = src[(int64_t)(t + N2 * k1) * N * N];
-      dft<N2, true>(v);
+      for (int q = 0; q < Q2; ++q) {
+        const int task = tid + q * NT;
+        if (EXACT || task < YC * N1 * ga) {
+          const int cc = task % YC, k1 = (task / YC) % N1, m = task / (YC * N1);
+          dft<N2, true>(pre[q]);
+          lds[(m * YC + cc) * P + N2 * k1] = pre[q][0];
 #pragma unroll
-      for (int t = 0; t < N2; ++t) lds[(m * YC + cc) * P + t + N2 * k1] = v[t];
+          for (int t = 1; t < N2; ++t)
+            lds[(m * YC + cc) * P + t + N2 * k1] = cmulc(pre[q][t], stw[k1 * N2 + t]);
+        }
+      }
+    } else {
+      for (int task = tid; task < YC * N1 * ga; task += NT) {
+        const int cc = task % YC, k1 = (task / YC) % N1, m = task / (YC * N1);
+        const cx<T>* __restrict__ src = sx + (int64_t)(q0 + m) * npts + cc;
+        cx<T> v[N2];
+#pragma unroll
+        for (int t = 0; t < N2; ++t) v[t] = src[(int64_t)(t + N2 * k1) * N * N];
+        dft<N2, true>(v);
+#pragma unroll
+        for (int t = 0; t < N2; ++t) lds[(m * YC + cc) * P + t + N2 * k1] = v[t];
+      }
     }
     lds_barrier();
     // inverse z step 1 to natural z: tasks (t2, c, m)
@@ -493,13 +534,20 @@ __global__ __launch_bounds__((zinv_threads<T, N>())) void k_zinv_acc(
       const int t2 = task % N2, cc = (task / N2) % YC, m = task / (N2 * YC);
       cx<T> v[N1];
 #pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1)
-        v[k1] = cmulc(lds[(m * YC + cc) * P + t2 + N2 * k1], stw[k1 * N2 + t2]);
+      for (int k1 = 0; k1 < N1; ++k1) {
+        v[k1] = lds[(m * YC + cc) * P + t2 + N2 * k1];
+        if constexpr (!PF) v[k1] = cmulc(v[k1], stw[k1 * N2 + t2]);
+      }
       dft<N1, true>(v);
 #pragma unroll
       for (int j1 = 0; j1 < N1; ++j1) lds[(m * YC + cc) * P + t2 + N2 * j1] = v[j1];
     }
     lds_barrier();
+    if constexpr (PF) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (a + 1 < B) fetch(q0 + ga, DIAG ? (B - a) / 2 : G);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     if constexpr (!DIAG) {
       double accA = 0.0;
 #pragma unroll
