@@ -46,13 +46,22 @@ def three_pass_fits(n, bulk, block):
             and ((block // 2) * rows * (n + 1) + n) * 2 * bulk + 64 <= 163840)
 
 
+def rows_fused_fits(n, bulk, block):
+    """Large grids (no plane in LDS): does the fused inverse-z/W pass fit
+    (4 n threads, block/2 x 4 z rows in LDS)?"""
+    return (not plane_fits(n, bulk) and 4 * n <= 1024
+            and ((block // 2) * 4 * (n + 1) + n) * 2 * bulk + 64 <= 163840)
+
+
 def tile_plan(n_orb, block, n=None, bulk=8, four_pass=False):
-    """(bi, bj, diag, npack, three) for every tile of the unmasked schedule;
-    `three`: the tile takes the three-pass schedule (a full tile on a grid
-    whose kernels fit)."""
+    """(bi, bj, diag, npack, fused) for every tile of the unmasked schedule;
+    `fused`: the tile's inverse z transform is fused with the W update (a
+    full tile; three passes where a plane fits, else the large-grid
+    schedule)."""
     out = []
     nb = (n_orb + block - 1) // block
-    fits = n is not None and not four_pass and three_pass_fits(n, bulk, block)
+    fits = n is not None and not four_pass and (three_pass_fits(n, bulk, block)
+                                                or rows_fused_fits(n, bulk, block))
     for I in range(nb):
         for J in range(I, nb):
             bi = min(block, n_orb - I * block)
@@ -69,7 +78,8 @@ def algorithmic_bytes(stage, tiles, npts, bulk, plane=True):
 
     Per packed transform (two pairs) and grid point: yz_fwd writes one
     complex value; x_poisson (the middle pass) reads and writes one; yz_inv
-    (four-pass tiles only) reads and writes one; w_accumulate reads one.
+    (tiles without the fused inverse z; on large grids the inverse y lines of
+    fused tiles) reads and writes one; w_accumulate reads one.
     Orbital traffic is counted once per tile: yz_fwd reads the tile's
     orbitals (8 B/pt each); w_accumulate reads them and reads + writes their
     W rows (24 B/pt each).
@@ -79,12 +89,15 @@ def algorithmic_bytes(stage, tiles, npts, bulk, plane=True):
     # pass: one extra read and write of the complex grid each way
     extra = 0 if plane else 2 * c
     tot = 0
-    for bi, bj, diag, npack, three in tiles:
+    for bi, bj, diag, npack, fused in tiles:
         orbs = bi if diag else bi + bj
         if stage == "yz_fwd":
             tot += (npack * (c + extra) + orbs * 8) * npts
         elif stage == "yz_inv":
-            tot += 0 if three else npack * (2 * c + extra) * npts
+            if fused:
+                tot += 0 if plane else npack * 2 * c * npts
+            else:
+                tot += npack * (2 * c + extra) * npts
         elif stage == "x_poisson":
             tot += npack * 2 * c * npts
         elif stage == "w_accumulate":

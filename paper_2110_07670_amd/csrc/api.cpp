@@ -459,11 +459,14 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
   // Full tiles take three passes where the kernels fit (the inverse z
   // transform feeds the W update directly); the others take four.
   void* S = w + p->off_S;
-  const bool three_ok =
-      p->schedule == ACE_SCHEDULE_AUTO && !bt.masked && acex::three_pass_ok(p->n, p->prec, B);
+  const bool fuse_ok = p->schedule == ACE_SCHEDULE_AUTO && !bt.masked;
+  const bool three_ok = fuse_ok && acex::three_pass_ok(p->n, p->prec, B);
+  const bool rows_ok = fuse_ok && acex::fused_rows_ok(p->n, p->prec, B);
   for (size_t ti = 0; ti < bt.tiles.size(); ++ti) {
     const Tile& t = bt.tiles[ti];
-    const bool three = three_ok && t.bi == B && t.bj == B;
+    const bool full = t.bi == B && t.bj == B;
+    const bool three = three_ok && full;           // plane-fitting grids
+    const bool fused = (three_ok || rows_ok) && full;
     const int* t_orbs = d_orbs + ti * (size_t)2 * B;
     const int chunk = p->chunk > 0 ? p->chunk : t.npack;
     for (int c0 = 0; c0 < t.npack; c0 += chunk) {
@@ -481,13 +484,13 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
       }
       if (!three) {
         ProfScope ps(p, 2, s);
-        e = acex::launch_inv_yz(g, Sc, cnt, s);
+        e = fused ? acex::launch_inv_y(g, Sc, cnt, s) : acex::launch_inv_yz(g, Sc, cnt, s);
         if (e != hipSuccess) return hip_fail(e);
       }
     }
     {
       ProfScope ps(p, 3, s);
-      if (three) {
+      if (fused) {
         e = acex::launch_zinv_acc(g, B, t.diag, S, phi, W, t_orbs, p->alpha, s);
       } else {
         const bool full = !bt.masked && t.bi == B && t.bj == B;

@@ -45,6 +45,11 @@ hipError_t launch_fwd_yz(const GridArgs& g, const void* phi, const Pack* packs, 
 // transforms, S + 0 .. npack-1 in the canonical row order, folded into W of
 // the tile's orbitals orbs[0..2 block)).
 bool three_pass_ok(int n, int prec, int block);
+// Large-grid schedule for full tiles where a plane does not fit
+// (fused_rows_ok): launch_fwd_yz -> launch_poisson_x -> launch_inv_y (the
+// inverse y lines only) -> launch_zinv_acc (inverse z rows folded into W).
+bool fused_rows_ok(int n, int prec, int block);
+hipError_t launch_inv_y(const GridArgs& g, void* S, int npack, hipStream_t s);
 hipError_t launch_mid(const GridArgs& g, void* S, int npack, hipStream_t s);
 hipError_t launch_zinv_acc(const GridArgs& g, int block, bool diag, const void* S,
                            const double* phi, double* W, const int* orbs, double alpha,

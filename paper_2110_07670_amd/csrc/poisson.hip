@@ -75,13 +75,12 @@ constexpr int line_threads() {
 }
 
 // rows per row-pass workgroup (fallback)
-constexpr int kRowsPerBlock = 8;
+constexpr int kRowsPerBlock = 16;
 template <int N>
 constexpr int row_threads() {
-  constexpr int t = kRowsPerBlock * fft_split<N>::N2;
-  int nt = ((t + 63) / 64) * 64;
-  while (nt % fft_split<N>::N2 != 0) nt += 64;
-  return nt;
+  constexpr int n1 = fft_split<N>::N1, n2 = fft_split<N>::N2;
+  constexpr int t = kRowsPerBlock * (n1 > n2 ? n1 : n2);
+  return ((t + 63) / 64) * 64;
 }
 
 // Workgroup barrier that orders LDS only: waits for this wave's LDS accesses
@@ -421,16 +420,19 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
 // Rows of y per inverse-z workgroup (one workgroup: rows x N points).  Eight
 // rows read 128 B (FP64) of each scratch row per transform; four rows (64 B
 // segments, two workgroups per CU) measured slower.
-template <typename T>
-constexpr int zinv_rows() { return 8; }
+// ROWS: the large-grid schedule, whose scratch is S[x][y][kz] (each z row
+// contiguous, so four rows per workgroup read whole rows).
+template <typename T, bool ROWS = false>
+constexpr int zinv_rows() { return ROWS ? 4 : 8; }
 
-template <typename T, int N>
-constexpr int zinv_threads() { return zinv_rows<T>() * N; }
+template <typename T, int N, bool ROWS = false>
+constexpr int zinv_threads() { return zinv_rows<T, ROWS>() * N; }
 
-template <typename T, int N, int B>
+template <typename T, int N, int B, bool ROWS = false>
 constexpr bool zinv_ok() {
-  return plane_ok<T, N>() && zinv_threads<T, N>() <= 1024 &&
-         ((long)(B / 2) * zinv_rows<T>() * (N + 1) + N) * (long)sizeof(cx<T>) + 64 <= kLdsBytes;
+  return (ROWS ? !plane_ok<T, N>() : plane_ok<T, N>()) && zinv_threads<T, N, ROWS>() <= 1024 &&
+         ((long)(B / 2) * zinv_rows<T, ROWS>() * (N + 1) + N) * (long)sizeof(cx<T>) + 64 <=
+             kLdsBytes;
 }
 
 // A workgroup owns the points (x, y0 .. y0 + YC - 1, all z) of a full B x B tile and
@@ -439,12 +441,16 @@ constexpr bool zinv_ok() {
 // them into the W sums it keeps in registers.  Off-diagonal tiles: W_a is
 // updated once per row (sum_b v_ab phi_b) and the B sums of W_J at the end;
 // diagonal tiles: all B sums at the end.  Fixed order, no atomics.
-template <typename T, int N, int B, bool DIAG>
-__global__ __launch_bounds__((zinv_threads<T, N>())) void k_zinv_acc(
+template <typename T, int N, int B, bool DIAG, bool ROWS>
+__global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
     const cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, const double* __restrict__ phi,
     double* __restrict__ W, const int* __restrict__ orbs, double alpha, int64_t npts) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
-  constexpr int NT = zinv_threads<T, N>(), G = B / 2, YC = zinv_rows<T>();
+  constexpr int NT = zinv_threads<T, N, ROWS>(), G = B / 2, YC = zinv_rows<T, ROWS>();
+  // kz positions and rows in the scratch: S[kz][x][y] (kz stride N^2, rows
+  // adjacent) or, with ROWS, S[x][y][kz] (kz adjacent, rows N apart)
+  constexpr int64_t KS = ROWS ? 1 : (int64_t)N * N;
+  constexpr int64_t CS = ROWS ? N : 1;
   static_assert(B % 2 == 0, "rows of a full tile pack evenly");
   __shared__ cx<T> lds[G * YC * P];
   __shared__ cx<T> stw[N];
@@ -455,7 +461,21 @@ __global__ __launch_bounds__((zinv_threads<T, N>())) void k_zinv_acc(
   // this thread's point for the W update (consecutive threads: consecutive z)
   const int c = tid / N, z = tid % N;
   const int64_t r = ((int64_t)x * N + y0 + c) * N + z;
-  const cx<T>* __restrict__ sx = S + (int64_t)x * N + y0;  // + pack*npts + pz*N*N + c
+  const cx<T>* __restrict__ sx =
+      S + (ROWS ? ((int64_t)x * N + y0) * N : (int64_t)x * N + y0);  // + pack npts + c CS + pz KS
+  // step-2 task -> (row, k1, transform): row fastest for S[kz][x][y] (the
+  // rows' values at one kz are adjacent), k1 fastest with ROWS (a row's
+  // positions are adjacent)
+  auto task_map = [&](int task, int& cc, int& k1, int& m) __attribute__((always_inline)) {
+    if constexpr (ROWS) {
+      k1 = task % N1;
+      cc = (task / N1) % YC;
+    } else {
+      cc = task % YC;
+      k1 = (task / YC) % N1;
+    }
+    m = task / (YC * N1);
+  };
 
   // off-diagonal: ph = phi_J, acc = W_J sums; diagonal: the tile's B orbitals
   double ph[B], acc[B];
@@ -484,10 +504,11 @@ __global__ __launch_bounds__((zinv_threads<T, N>())) void k_zinv_acc(
     for (int q = 0; q < Q2; ++q) {
       const int task = tid + q * NT;
       if (EXACT || task < YC * N1 * gan) {
-        const int cc = task % YC, k1 = (task / YC) % N1, m = task / (YC * N1);
-        const cx<T>* __restrict__ src = sx + (int64_t)(q0n + m) * npts + cc;
+        int cc, k1, m;
+        task_map(task, cc, k1, m);
+        const cx<T>* __restrict__ src = sx + (int64_t)(q0n + m) * npts + cc * CS;
 #pragma unroll
-        for (int t = 0; t < N2; ++t) pre[q][t] = src[(int64_t)(t + N2 * k1) * N * N];
+        for (int t = 0; t < N2; ++t) pre[q][t] = src[(int64_t)(t + N2 * k1) * KS];
       }
     }
   };
@@ -508,7 +529,8 @@ __global__ __launch_bounds__((zinv_threads<T, N>())) void k_zinv_acc(
       for (int q = 0; q < Q2; ++q) {
         const int task = tid + q * NT;
         if (EXACT || task < YC * N1 * ga) {
-          const int cc = task % YC, k1 = (task / YC) % N1, m = task / (YC * N1);
+          int cc, k1, m;
+          task_map(task, cc, k1, m);
           dft<N2, true>(pre[q]);
           lds[(m * YC + cc) * P + N2 * k1] = pre[q][0];
 #pragma unroll
@@ -518,11 +540,12 @@ __global__ __launch_bounds__((zinv_threads<T, N>())) void k_zinv_acc(
       }
     } else {
       for (int task = tid; task < YC * N1 * ga; task += NT) {
-        const int cc = task % YC, k1 = (task / YC) % N1, m = task / (YC * N1);
-        const cx<T>* __restrict__ src = sx + (int64_t)(q0 + m) * npts + cc;
+        int cc, k1, m;
+        task_map(task, cc, k1, m);
+        const cx<T>* __restrict__ src = sx + (int64_t)(q0 + m) * npts + cc * CS;
         cx<T> v[N2];
 #pragma unroll
-        for (int t = 0; t < N2; ++t) v[t] = src[(int64_t)(t + N2 * k1) * N * N];
+        for (int t = 0; t < N2; ++t) v[t] = src[(int64_t)(t + N2 * k1) * KS];
         dft<N2, true>(v);
 #pragma unroll
         for (int t = 0; t < N2; ++t) lds[(m * YC + cc) * P + t + N2 * k1] = v[t];
@@ -591,7 +614,7 @@ __global__ __launch_bounds__((zinv_threads<T, N>())) void k_zinv_acc(
 
 // ------------------------------------------------------------------ z rows (fallback)
 // Forward: pair density + z transform of kRowsPerBlock consecutive rows,
-// written in position order.
+// written in position order.  Twiddles in LDS as stw[k1 N2 + t2].
 template <typename T, int N>
 __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
     const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
@@ -599,20 +622,21 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
   constexpr int NT = row_threads<N>(), R = kRowsPerBlock;
   __shared__ cx<T> lds[R * P];
-  constexpr int nrb = N * N / R;
-  const int rb = blockIdx.x % nrb, p = blockIdx.x / nrb;
+  __shared__ cx<T> stw[N];
+  // transform fastest: consecutive workgroups share the row block, so the
+  // orbital rows stay in L2 across the tile's transforms
+  const int p = blockIdx.x % npack, rb = blockIdx.x / npack;
   const Pack pk = packs[p];
-  const int tid = threadIdx.x, t2 = tid % N2;
-  cx<T> w[N1];
-#pragma unroll
-  for (int k1 = 0; k1 < N1; ++k1) w[k1] = tw[t2 * k1];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];
   const int64_t row0 = (int64_t)rb * R * N;
   const T* __restrict__ pa = phi + (int64_t)pk.a * npts + row0;
   const T* __restrict__ pb = phi + (int64_t)pk.b * npts + row0;
   const bool two = pk.c >= 0;
   const T* __restrict__ pd = phi + (int64_t)(two ? pk.d : pk.b) * npts + row0;
+  __syncthreads();
   for (int task = tid; task < R * N2; task += NT) {
-    const int y = task / N2;
+    const int y = task / N2, t2 = task % N2;
     cx<T> v[N1];
 #pragma unroll
     for (int j1 = 0; j1 < N1; ++j1) {
@@ -622,7 +646,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
     }
     dft<N1, false>(v);
 #pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], w[k1]);
+    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[k1 * N2 + t2]);
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) lds[y * P + t2 + N2 * k1] = v[k1];
   }
@@ -648,12 +672,11 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
   constexpr int NT = row_threads<N>(), R = kRowsPerBlock;
   __shared__ cx<T> lds[R * P];
+  __shared__ cx<T> stw[N];
   constexpr int nrb = N * N / R;
   const int rb = blockIdx.x % nrb, p = blockIdx.x / nrb;
-  const int tid = threadIdx.x, t2 = tid % N2;
-  cx<T> w[N1];
-#pragma unroll
-  for (int k1 = 0; k1 < N1; ++k1) w[k1] = tw[t2 * k1];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];
   cx<T>* __restrict__ io = S + (int64_t)p * npts + (int64_t)rb * R * N;
   for (int e = tid; e < R * N; e += NT) lds[(e / N) * P + (e % N)] = io[e];
   __syncthreads();
@@ -668,10 +691,10 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
   }
   __syncthreads();
   for (int task = tid; task < R * N2; task += NT) {
-    const int y = task / N2;
+    const int y = task / N2, t2 = task % N2;
     cx<T> v[N1];
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[y * P + t2 + N2 * k1], w[k1]);
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[y * P + t2 + N2 * k1], stw[k1 * N2 + t2]);
     dft<N1, true>(v);
 #pragma unroll
     for (int j1 = 0; j1 < N1; ++j1) io[y * N + t2 + N2 * j1] = v[j1];
@@ -1041,18 +1064,41 @@ static hipError_t mid_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+template <typename T, int N, int B, bool ROWS>
+static hipError_t zinv_launch(const GridArgs& g, bool diag, const void* S, const double* phi,
+                              double* W, const int* orbs, double alpha, hipStream_t s) {
+  if constexpr (zinv_ok<T, N, B, ROWS>()) {
+    const dim3 grid(N * (N / zinv_rows<T, ROWS>())), block(zinv_threads<T, N, ROWS>());
+    if (diag)
+      hipLaunchKernelGGL((k_zinv_acc<T, N, B, true, ROWS>), grid, block, 0, s,
+                         static_cast<const cx<T>*>(S), static_cast<const cx<T>*>(g.tw), phi, W,
+                         orbs, alpha, g.npts);
+    else
+      hipLaunchKernelGGL((k_zinv_acc<T, N, B, false, ROWS>), grid, block, 0, s,
+                         static_cast<const cx<T>*>(S), static_cast<const cx<T>*>(g.tw), phi, W,
+                         orbs, alpha, g.npts);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T, int N, int B>
 static hipError_t zinv_t(const GridArgs& g, bool diag, const void* S, const double* phi,
                          double* W, const int* orbs, double alpha, hipStream_t s) {
-  if constexpr (zinv_ok<T, N, B>()) {
-    if (diag)
-      hipLaunchKernelGGL((k_zinv_acc<T, N, B, true>), dim3(N * (N / zinv_rows<T>())),
-                         dim3(zinv_threads<T, N>()), 0, s, static_cast<const cx<T>*>(S),
-                         static_cast<const cx<T>*>(g.tw), phi, W, orbs, alpha, g.npts);
-    else
-      hipLaunchKernelGGL((k_zinv_acc<T, N, B, false>), dim3(N * (N / zinv_rows<T>())),
-                         dim3(zinv_threads<T, N>()), 0, s, static_cast<const cx<T>*>(S),
-                         static_cast<const cx<T>*>(g.tw), phi, W, orbs, alpha, g.npts);
+  if constexpr (plane_ok<T, N>())
+    return zinv_launch<T, N, B, false>(g, diag, S, phi, W, orbs, alpha, s);
+  else
+    return zinv_launch<T, N, B, true>(g, diag, S, phi, W, orbs, alpha, s);
+}
+
+// the large-grid schedule's inverse y lines (its inverse z is fused with W)
+template <typename T, int N>
+static hipError_t inv_y_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
+  if constexpr (!plane_ok<T, N>()) {
+    hipLaunchKernelGGL((k_lines<T, N, MODE_INV>), dim3((N / line_chunk<N>()) * N * npack),
+                       dim3(line_threads<N>()), 0, s, static_cast<cx<T>*>(S),
+                       static_cast<const cx<T>*>(g.tw), npack, g.npts, (int64_t)N, (int64_t)N * N,
+                       T(0), T(0), T(0), T(0), (double*)nullptr);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
@@ -1120,6 +1166,32 @@ bool three_pass_ok(int n, int prec, int block) {
     ACEX_SIZES(X)
 #undef X
     default: return false;
+  }
+}
+
+bool fused_rows_ok(int n, int prec, int block) {
+  switch (n) {
+#define X(N)                                                                                \
+  case N:                                                                                   \
+    if (block == 16)                                                                        \
+      return prec == 0 ? zinv_ok<double, N, 16, true>() : zinv_ok<float, N, 16, true>();    \
+    if (block == 8)                                                                         \
+      return prec == 0 ? zinv_ok<double, N, 8, true>() : zinv_ok<float, N, 8, true>();      \
+    return false;
+    ACEX_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
+hipError_t launch_inv_y(const GridArgs& g, void* S, int npack, hipStream_t s) {
+  if (npack <= 0) return hipSuccess;
+  switch (g.n) {
+#define X(N) \
+  case N: return g.prec == 0 ? inv_y_t<double, N>(g, S, npack, s) : inv_y_t<float, N>(g, S, npack, s);
+    ACEX_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -102,3 +102,32 @@ def test_three_pass_fp32_matches_four_pass(lib, n):
     assert O.rel_err(three["W"], four["W"]) < 1e-6
     assert O.rel_err(three["W"], ref["W"]) < 1e-6
     assert abs(three["ex"][0] - ref["ex"][0]) < 1e-6 * abs(ref["ex"][0])
+
+
+@pytest.mark.parametrize("n", [120, 144])
+def test_fused_rows_large_grids_fp64(lib, n):
+    """Grids whose plane does not fit LDS: the large-grid schedule fuses the
+    inverse z rows with the W update on full tiles (blocks of 8 here)."""
+    _say("large-grid fused schedule fp64 n=%d orbitals 16 block 8" % n)
+    L = 0.11 * n + 5.0
+    spec = synth.SystemSpec("t3L", L, n, 16, "random", 0, (1.0, 1.4), 0.25, 600 + n)
+    s = synth.build_system(spec)
+    fused, four = _both(lib, spec, s.phi, "fp64", 8)
+    W_ref = O.apply_vx(s.phi, spec.cell, spec.alpha, workers=8)
+    assert fused["info"][0] == 0
+    assert O.rel_err(fused["W"], W_ref) < TOL
+    assert O.rel_err(fused["W"], four["W"]) < 1e-13
+    assert O.rel_err(fused["xi"], four["xi"]) < 1e-12
+
+
+@pytest.mark.parametrize("n", [144, 160, 192])
+def test_fused_rows_large_grids_fp32(lib, n):
+    _say("large-grid fused schedule fp32 n=%d orbitals 32" % n)
+    spec = synth.SystemSpec("t3Lf", 0.11 * n + 5.0, n, 32, "random", 0, (1.0, 1.4), 0.25, 700 + n)
+    s = synth.build_system(spec)
+    fused, four = _both(lib, spec, s.phi, "fp32", 16)
+    p64 = lib.Plan(spec.n, (spec.L,) * 3, 32, "fp64", spec.alpha)
+    ref = _host(lib.ace_build(p64, _dev(s.phi)))
+    assert O.rel_err(fused["W"], four["W"]) < 1e-6
+    assert O.rel_err(fused["W"], ref["W"]) < 1e-6
+    assert abs(fused["ex"][0] - ref["ex"][0]) < 1e-6 * abs(ref["ex"][0])
