@@ -32,6 +32,7 @@ struct Tile {
   bool diag;
   int pack0, npack;
   unsigned useI, useJ;  // local orbitals with at least one kept pair
+  bool complete;        // every pair of the tile kept: canonical pack order
 };
 
 struct ProfRec {
@@ -228,7 +229,7 @@ void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& p
       t.diag = (I == J);
       t.pack0 = (int)packs.size();
       t.useI = t.useJ = 0u;
-      int local = 0;
+      int local = 0, kept = 0;
       for (int a = 0; a < t.bi; ++a) {
         int half = 0;
         Pack cur{-1, -1, -1, -1};
@@ -236,6 +237,7 @@ void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& p
         for (int b = t.diag ? a : 0; b < t.bj; ++b) {
           const int i = ord[t.i0 + a], j = ord[t.j0 + b];
           if (!mask_on(mask, k, std::min(i, j), std::max(i, j))) continue;
+          ++kept;
           t.useI |= 1u << a;
           if (t.diag) t.useI |= 1u << b;
           else t.useJ |= 1u << b;
@@ -259,6 +261,7 @@ void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& p
         }
       }
       t.npack = local;
+      t.complete = kept == (t.diag ? t.bi * (t.bi + 1) / 2 : t.bi * t.bj);
       if (t.npack > 0) {
         tiles.push_back(t);
         for (int a = 0; a < B; ++a) orbs.push_back(a < t.bi ? ord[t.i0 + a] : -1);
@@ -459,12 +462,13 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
   // Full tiles take three passes where the kernels fit (the inverse z
   // transform feeds the W update directly); the others take four.
   void* S = w + p->off_S;
-  const bool fuse_ok = p->schedule == ACE_SCHEDULE_AUTO && !bt.masked;
+  const bool fuse_ok = p->schedule == ACE_SCHEDULE_AUTO;
   const bool three_ok = fuse_ok && acex::three_pass_ok(p->n, p->prec, B);
   const bool rows_ok = fuse_ok && acex::fused_rows_ok(p->n, p->prec, B);
   for (size_t ti = 0; ti < bt.tiles.size(); ++ti) {
     const Tile& t = bt.tiles[ti];
-    const bool full = t.bi == B && t.bj == B;
+    // a full block x block tile with every pair kept (masked builds too)
+    const bool full = t.bi == B && t.bj == B && t.complete;
     const bool three = three_ok && full;           // plane-fitting grids
     const bool fused = (three_ok || rows_ok) && full;
     const int* t_orbs = d_orbs + ti * (size_t)2 * B;
@@ -493,7 +497,7 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
       if (fused) {
         e = acex::launch_zinv_acc(g, B, t.diag, S, phi, W, t_orbs, p->alpha, s);
       } else {
-        const bool full = !bt.masked && t.bi == B && t.bj == B;
+        const bool full = t.bi == B && t.bj == B && t.complete;
         e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,
                                     full ? nullptr : d_meta + t.pack0, t.npack, t_orbs, t.useI,
                                     t.useJ, p->alpha, p->npts, s);

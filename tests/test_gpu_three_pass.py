@@ -131,3 +131,20 @@ def test_fused_rows_large_grids_fp32(lib, n):
     assert O.rel_err(fused["W"], four["W"]) < 1e-6
     assert O.rel_err(fused["W"], ref["W"]) < 1e-6
     assert abs(fused["ex"][0] - ref["ex"][0]) < 1e-6 * abs(ref["ex"][0])
+
+
+@pytest.mark.parametrize("n", [48, 120])
+def test_masked_build_fuses_complete_tiles(lib, n):
+    """A mask that drops two pairs: the tiles holding them take the masked
+    four-pass path, every other (complete) tile the fused one."""
+    _say("masked build with complete tiles n=%d orbitals 24 block 8" % n)
+    spec = synth.SystemSpec("t3m", 0.11 * n + 5.0, n, 24, "random", 0, (1.0, 1.4), 0.25, 800 + n)
+    s = synth.build_system(spec)
+    mask = np.ones((24, 24), dtype=np.uint8)
+    mask[2, 13] = mask[13, 2] = 0     # tile (0, 1)
+    mask[17, 17] = 0                  # tile (2, 2), a diagonal pair
+    p = lib.Plan(spec.n, (spec.L,) * 3, 24, "fp64", spec.alpha)
+    p.set_tiling(8)
+    got = _host(lib.ace_build(p, _dev(s.phi), pair_mask=mask))
+    W_ref = O.apply_vx(s.phi, spec.cell, spec.alpha, pair_mask=mask.astype(bool), workers=8)
+    assert O.rel_err(got["W"], W_ref) < TOL
