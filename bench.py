@@ -175,6 +175,8 @@ def run_screened(args):
         wts = torch.from_numpy(screening.weights_to_array(params)).to(dev)
     phi = torch.from_numpy(system.phi).to(dev)
     plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, args.precision, spec.alpha)
+    if args.tiling:
+        plan.set_tiling(*[int(v) for v in args.tiling.split(",")])
     ws = _lib.workspace(plan.workspace_bytes(), dev)
     ws_apply = _lib.workspace(plan.apply_workspace_bytes(spec.n_orb), dev)
     W = torch.empty_like(phi)
