@@ -418,8 +418,9 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
 }
 
 // Rows of y per inverse-z workgroup (one workgroup: rows x N points).  Eight
-// rows read 128 B (FP64) of each scratch row per transform; four rows (64 B
-// segments, two workgroups per CU) measured slower.
+// rows read 128 B (FP64) of each scratch row per transform; four FP64 rows
+// (64 B segments, two workgroups per CU) measured slower, even with the two
+// halves of each segment dispatched back to back on one XCD.
 // ROWS: the large-grid schedule, whose scratch is S[x][y][kz] (each z row
 // contiguous, so four rows per workgroup read whole rows).
 template <typename T, bool ROWS = false>
@@ -456,7 +457,20 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
   const int bid = blockIdx.x;
-  const int y0 = (bid % (N / YC)) * YC, x = bid / (N / YC);
+  int x, y0;
+  if constexpr (!ROWS && YC * sizeof(cx<T>) < 128) {
+    // two workgroups share each 128-byte scratch segment: they run back to
+    // back on one XCD (workgroup b runs on XCD b mod 8), so the second finds
+    // the lines in L2
+    constexpr int H = 128 / (YC * int(sizeof(cx<T>)));  // workgroups per segment
+    const int g = bid >> 3, xcd = bid & 7;
+    const int seg = (g / H) * 8 + xcd;
+    y0 = (seg % (N / (H * YC))) * (H * YC) + (g % H) * YC;
+    x = seg / (N / (H * YC));
+  } else {
+    y0 = (bid % (N / YC)) * YC;
+    x = bid / (N / YC);
+  }
   for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];  // stw[k1 N2 + t2] = w^(t2 k1)
   // this thread's point for the W update (consecutive threads: consecutive z)
   const int c = tid / N, z = tid % N;
