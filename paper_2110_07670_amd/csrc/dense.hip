@@ -160,7 +160,7 @@ hipError_t launch_gemm_abt(const double* A, const double* B, int m, int n, int64
 // ------------------------------------------------------------------ Out = A B (A small)
 // Workgroup: 256 threads, output tile 64 rows x 128 columns; wave w owns
 // rows [16 w, 16 w + 16) x 128 columns = 8 MFMA blocks.  Rows beyond 64 are
-// covered by more workgroups along grid y.  Next K-slab prefetched into
+// covered by more workgroups (row blocks).  Next K-slab prefetched into
 // registers.
 constexpr int kAbRows = 64;
 constexpr int kAbCols = 128;
@@ -175,8 +175,18 @@ __global__ __launch_bounds__(256) void k_gemm_ab(const double* __restrict__ A,
   if (skip && *skip != 0) return;
   __shared__ double sA[kAbRows * (kAbKT + 1)];
   __shared__ double sB[kAbKT * kAbCols];
-  const int64_t r0 = (int64_t)blockIdx.x * kAbCols;
-  const int m0 = blockIdx.y * kAbRows;
+  // Workgroup b runs on XCD b mod 8: the row blocks of one column block are
+  // consecutive on one XCD, so B's columns are read from HBM once and the
+  // other row blocks find them in that XCD's L2.
+  const int nrb = (m + kAbRows - 1) / kAbRows;
+  const int64_t ncb = (R + kAbCols - 1) / kAbCols;
+  const int64_t g = blockIdx.x >> 3;
+  const int xcd = blockIdx.x & 7;
+  const int rblk = (int)(g % nrb);
+  const int64_t cblk = (g / nrb) * 8 + xcd;
+  if (cblk >= ncb) return;
+  const int64_t r0 = cblk * kAbCols;
+  const int m0 = rblk * kAbRows;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   d4 acc[8];
 #pragma unroll
@@ -233,8 +243,11 @@ __global__ __launch_bounds__(256) void k_gemm_ab(const double* __restrict__ A,
 
 hipError_t launch_gemm_ab(const double* A, const double* B, int m, int k, int64_t R, double scale,
                           double* Out, const int* skip, hipStream_t s) {
-  const dim3 grid((unsigned)((R + kAbCols - 1) / kAbCols), (unsigned)((m + kAbRows - 1) / kAbRows));
-  hipLaunchKernelGGL(k_gemm_ab, grid, dim3(256), 0, s, A, B, m, k, R, scale, Out, skip);
+  const int64_t ncb = (R + kAbCols - 1) / kAbCols;
+  const int64_t nrb = (m + kAbRows - 1) / kAbRows;
+  const int64_t blocks = ((ncb + 7) / 8) * 8 * nrb;  // column blocks padded to the 8 XCDs
+  hipLaunchKernelGGL(k_gemm_ab, dim3((unsigned)blocks), dim3(256), 0, s, A, B, m, k, R, scale,
+                     Out, skip);
   return hipGetLastError();
 }
 
