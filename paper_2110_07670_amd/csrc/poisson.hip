@@ -838,77 +838,87 @@ __global__ __launch_bounds__((line_threads<N, C>())) void k_lines(
 // ------------------------------------------------------------------ W accumulation
 // One thread per grid point; the tile's pairs are visited in a fixed order
 // (no atomics), so W is bitwise reproducible.  orbs: the tile's orbitals,
-// I list (B entries) then J list (B entries).  General (masked) tiles: a
-// runtime loop over the tile's transforms with unconditional loads (so they
-// pipeline); meta[p] = a0 | b0 << 8 | a1 << 16 | b1 << 24 gives the local
-// positions of the pair in the real (a0, b0) and imaginary (a1, b1; a1 = 255
-// when absent) half; useI / useJ flag the orbitals with at least one pair.
-
-// arr[idx] for a uniform runtime idx, as selects over the positions (every
-// element keeps a static index, so the arrays stay in registers)
-template <int B>
-__device__ __forceinline__ double reg_get(const double (&arr)[B], int idx) {
-  double v = 0.0;
-  sfor<0, B>([&](auto c) {
-    constexpr int k = decltype(c)::value;
-    v = (idx == k) ? arr[k] : v;
-  });
-  return v;
-}
-template <int B>
-__device__ __forceinline__ void reg_add(double (&arr)[B], int idx, double v) {
-  sfor<0, B>([&](auto c) {
-    constexpr int k = decltype(c)::value;
-    arr[k] += (idx == k) ? v : 0.0;
-  });
-}
+// I list (B entries) then J list (B entries).
+//
+// General (masked) tiles: meta[p] = a0 | b0 << 8 | a1 << 16 | b1 << 24 gives
+// the local positions of transform p's pair in the real (a0, b0) and
+// imaginary (a1, b1; a1 = 255 when absent) half; useI / useJ flag the
+// orbitals with at least one pair.  Transforms come row-major in a (both
+// halves share it), so a thread keeps the current row's orbital value and
+// accumulator in registers and the other side's values and accumulators in
+// LDS, laid out [orbital][thread]: each thread reads and writes only its own
+// column (no barriers, no bank conflicts), and the runtime positions b index
+// LDS instead of select chains over registers.  The sums run in the same
+// order as a per-orbital register accumulator would take them.
+constexpr int kAccThreads = 128;
+constexpr int kAccAhead = 8;  // transforms whose loads are issued ahead
 
 template <typename TS, int B, bool DIAG>
-__global__ __launch_bounds__(256) void k_accumulate(
+__global__ __launch_bounds__(kAccThreads) void k_accumulate(
     const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W,
     const int* __restrict__ meta, int npack, const int* __restrict__ orbs, unsigned useI,
     unsigned useJ, double alpha, int64_t npts) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r >= npts) return;
-  double phI[B], accI[B];
-  double phJ[DIAG ? 1 : B], accJ[DIAG ? 1 : B];
+  __shared__ double sph[B][kAccThreads], sacc[B][kAccThreads];
+  const int t = threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * kAccThreads + t;
+  if (r >= npts) return;  // no barriers below
+  // the other side: the J list off the diagonal, the tile's one list on it
+  const unsigned use = DIAG ? useI : useJ;
+  const int* side = DIAG ? orbs : orbs + B;
 #pragma unroll
-  for (int a = 0; a < B; ++a) {
-    phI[a] = ((useI >> a) & 1u) ? phi[(int64_t)orbs[a] * npts + r] : 0.0;
-    accI[a] = 0.0;
+  for (int b = 0; b < B; ++b) {
+    sph[b][t] = ((use >> b) & 1u) ? phi[(int64_t)side[b] * npts + r] : 0.0;
+    sacc[b][t] = 0.0;
   }
-  if constexpr (!DIAG) {
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      phJ[b] = ((useJ >> b) & 1u) ? phi[(int64_t)orbs[B + b] * npts + r] : 0.0;
-      accJ[b] = 0.0;
-    }
-  }
-  auto pair = [&](int a, int b, double v) __attribute__((always_inline)) {
-    if constexpr (DIAG) {
-      reg_add<B>(accI, a, v * reg_get<B>(phI, b));
-      if (a != b) reg_add<B>(accI, b, v * reg_get<B>(phI, a));
+  int cur = -1;  // current row a
+  double phA = 0.0, accA = 0.0;
+  auto pair = [&](int b, double v) __attribute__((always_inline)) {
+    if (DIAG && b == cur) {
+      accA += v * phA;
     } else {
-      reg_add<B>(accI, a, v * reg_get<B>(phJ, b));
-      reg_add<B>(accJ, b, v * reg_get<B>(phI, a));
+      accA += v * sph[b][t];
+      sacc[b][t] += v * phA;
     }
   };
-#pragma unroll 4
-  for (int p = 0; p < npack; ++p) {
-    const cx<TS> z = S[(int64_t)p * npts + r];
-    const int m = meta[p];
-    const int a0 = m & 255, b0 = (m >> 8) & 255, a1 = (m >> 16) & 255, b1 = (m >> 24) & 255;
-    pair(a0, b0, double(z.re));
-    if (a1 != 255) pair(a1, b1, double(z.im));
+  for (int p0 = 0; p0 < npack; p0 += kAccAhead) {
+    cx<TS> z[kAccAhead];
+    int m[kAccAhead];
+#pragma unroll
+    for (int u = 0; u < kAccAhead; ++u) {
+      const int p = min(p0 + u, npack - 1);
+      z[u] = S[(int64_t)p * npts + r];
+      m[u] = meta[p];
+    }
+#pragma unroll
+    for (int u = 0; u < kAccAhead; ++u) {
+      if (p0 + u >= npack) break;
+      const int a = m[u] & 255, b0 = (m[u] >> 8) & 255, a1 = (m[u] >> 16) & 255,
+                b1 = (m[u] >> 24) & 255;
+      if (a != cur) {
+        if (cur >= 0) {
+          if constexpr (DIAG) sacc[cur][t] = accA;
+          else W[(int64_t)orbs[cur] * npts + r] -= alpha * accA;
+        }
+        cur = a;
+        if constexpr (DIAG) {
+          phA = sph[a][t];
+          accA = sacc[a][t];  // contributions of earlier rows, where a was the column
+        } else {
+          phA = phi[(int64_t)orbs[a] * npts + r];
+          accA = 0.0;
+        }
+      }
+      pair(b0, double(z[u].re));
+      if (a1 != 255) pair(b1, double(z[u].im));
+    }
+  }
+  if (cur >= 0) {
+    if constexpr (DIAG) sacc[cur][t] = accA;
+    else W[(int64_t)orbs[cur] * npts + r] -= alpha * accA;
   }
 #pragma unroll
-  for (int a = 0; a < B; ++a)
-    if ((useI >> a) & 1u) W[(int64_t)orbs[a] * npts + r] -= alpha * accI[a];
-  if constexpr (!DIAG) {
-#pragma unroll
-    for (int b = 0; b < B; ++b)
-      if ((useJ >> b) & 1u) W[(int64_t)orbs[B + b] * npts + r] -= alpha * accJ[b];
-  }
+  for (int b = 0; b < B; ++b)
+    if ((use >> b) & 1u) W[(int64_t)side[b] * npts + r] -= alpha * sacc[b][t];
 }
 
 template <typename TS, int B, bool DIAG>
@@ -1292,12 +1302,13 @@ static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W, 
                          static_cast<const cx<TS>*>(S), phi, W, orbs, alpha, npts);
     return hipGetLastError();
   }
+  const dim3 grid_m((unsigned)((npts + kAccThreads - 1) / kAccThreads));
   if (diag)
-    hipLaunchKernelGGL((k_accumulate<TS, B, true>), grid, dim3(256), 0, s,
+    hipLaunchKernelGGL((k_accumulate<TS, B, true>), grid_m, dim3(kAccThreads), 0, s,
                        static_cast<const cx<TS>*>(S), phi, W, meta, npack, orbs, useI, useJ,
                        alpha, npts);
   else
-    hipLaunchKernelGGL((k_accumulate<TS, B, false>), grid, dim3(256), 0, s,
+    hipLaunchKernelGGL((k_accumulate<TS, B, false>), grid_m, dim3(kAccThreads), 0, s,
                        static_cast<const cx<TS>*>(S), phi, W, meta, npack, orbs, useI, useJ,
                        alpha, npts);
   return hipGetLastError();
