@@ -171,15 +171,17 @@ int ace_profile_read(ace_plan *plan, double *out_ms, int *out_count);
  * tile) and the x-pass pencils per workgroup (8, 16 or 32 dividing n; 0 =
  * the default).  chunk and pencils change no result bit; block changes
  * which pairs share a transform and the order of the W sums, so results move
- * by rounding only.  block and chunk change ace_workspace_bytes.
+ * by rounding only.  block changes ace_workspace_bytes (the scratch holds
+ * one tile's transforms: block^2 / 2 complex grids).
  * ACE_ERR_ARG for a value outside these sets. */
 int ace_plan_set_tiling(ace_plan *plan, int block, int chunk, int pencils);
 
 /* Transform schedule.  ACE_SCHEDULE_AUTO: full pair tiles (block x block
- * orbitals) of an unmasked build take three passes over the scratch grids where the
- * grid's plane fits a workgroup's LDS (FP64 n <= 96, FP32 n <= 128): the
- * inverse z transform feeds the W update directly; every other tile takes
- * four passes (inverse y/z written back, then the W update).
+ * orbitals, every pair kept; block 8 or 16) take three passes over the
+ * scratch grids where the grid's plane fits a workgroup's LDS (FP64 n <= 96,
+ * FP32 n <= 128) and five where it does not; in both the inverse z transform
+ * feeds the W update directly.  Every other tile takes four passes (inverse
+ * y/z written back, then the W update).
  * ACE_SCHEDULE_FOUR_PASS: four passes everywhere.  Both give the same result
  * up to rounding (the order of the W sums differs). */
 #define ACE_SCHEDULE_AUTO 0

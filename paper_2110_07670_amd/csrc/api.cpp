@@ -160,14 +160,22 @@ bool mask_on(const uint8_t* mask, int n_orb, int i, int j) {
 }
 
 // Orbital order for the pair tiles.  Without a mask: 0, 1, 2, ...  With a
-// mask: reverse Cuthill-McKee of the kept-pair graph (breadth-first from a
-// least-connected orbital, neighbours by increasing degree, ties by index,
-// reversed), so that kept pairs of spatially close orbitals gather in a band
-// and the tiles of consecutive blocks are dense while far tiles are empty.
-std::vector<int> pair_order(int k, const uint8_t* mask) {
-  std::vector<int> ord(k);
-  for (int i = 0; i < k; ++i) ord[i] = i;
-  if (!mask) return ord;
+// mask: greedy clusters of B orbitals joined by many kept pairs, so that the
+// kept pairs of spatially close orbitals gather in few, dense tiles (a band
+// order such as reverse Cuthill-McKee leaves the tiles of a 3-D system
+// sparse: measured on the 512-orbital screen, 30% more orbital traffic in
+// the W update and 7% more transforms).  A cluster starts at the unplaced
+// orbital with the fewest unplaced partners (ties: lowest index) and grows
+// by the unplaced orbital with the most kept pairs into the cluster (ties:
+// fewest unplaced partners, then lowest index); when no unplaced orbital has
+// a partner in the cluster, the start rule picks the next one.
+std::vector<int> pair_order(int k, int B, const uint8_t* mask) {
+  std::vector<int> ord;
+  ord.reserve(k);
+  if (!mask) {
+    for (int i = 0; i < k; ++i) ord.push_back(i);
+    return ord;
+  }
   std::vector<std::vector<int>> adj(k);
   for (int i = 0; i < k; ++i)
     for (int j = i + 1; j < k; ++j)
@@ -175,31 +183,40 @@ std::vector<int> pair_order(int k, const uint8_t* mask) {
         adj[i].push_back(j);
         adj[j].push_back(i);
       }
-  auto deg_less = [&](int a, int b) {
-    return adj[a].size() != adj[b].size() ? adj[a].size() < adj[b].size() : a < b;
+  std::vector<int> free_deg(k), conn(k, 0), cand;
+  std::vector<char> placed(k, 0);
+  for (int i = 0; i < k; ++i) free_deg[i] = (int)adj[i].size();
+  auto place = [&](int v) {
+    placed[v] = 1;
+    ord.push_back(v);
+    for (int w : adj[v]) {
+      --free_deg[w];
+      if (!placed[w] && conn[w]++ == 0) cand.push_back(w);
+    }
   };
-  for (auto& v : adj) std::sort(v.begin(), v.end(), deg_less);
-  std::vector<char> seen(k, 0);
-  std::vector<int> out;
-  out.reserve(k);
-  std::vector<int> by_deg(ord);
-  std::sort(by_deg.begin(), by_deg.end(), deg_less);
-  for (int start : by_deg) {
-    if (seen[start]) continue;
-    size_t head = out.size();
-    out.push_back(start);
-    seen[start] = 1;
-    while (head < out.size()) {
-      const int u = out[head++];
-      for (int v : adj[u])
-        if (!seen[v]) {
-          seen[v] = 1;
-          out.push_back(v);
-        }
+  auto start = [&]() {
+    int best = -1;
+    for (int v = 0; v < k; ++v)
+      if (!placed[v] && (best < 0 || free_deg[v] < free_deg[best])) best = v;
+    return best;
+  };
+  while ((int)ord.size() < k) {
+    for (int w : cand) conn[w] = 0;  // partners counted per cluster
+    cand.clear();
+    place(start());
+    for (int n = 1; n < B && (int)ord.size() < k; ++n) {
+      int best = -1;
+      for (int w : cand) {
+        if (placed[w]) continue;
+        if (best < 0 || conn[w] > conn[best] ||
+            (conn[w] == conn[best] &&
+             (free_deg[w] < free_deg[best] || (free_deg[w] == free_deg[best] && w < best))))
+          best = w;
+      }
+      place(best >= 0 ? best : start());
     }
   }
-  std::reverse(out.begin(), out.end());
-  return out;
+  return ord;
 }
 
 // Pair tiles for ace_build: blocks of B consecutive orbitals of `ord`; tile
@@ -214,7 +231,7 @@ void build_schedule(const ace_plan* p, const uint8_t* mask, std::vector<Pack>& p
                     std::vector<int>& meta, std::vector<int>& orbs, std::vector<Tile>& tiles) {
   const int B = p->block, k = p->n_orb;
   const int nb = (k + B - 1) / B;
-  const std::vector<int> ord = pair_order(k, mask);
+  const std::vector<int> ord = pair_order(k, B, mask);
   packs.clear();
   tiles.clear();
   meta.clear();

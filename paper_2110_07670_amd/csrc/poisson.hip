@@ -1292,8 +1292,8 @@ template <typename TS, int B>
 static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W, const int* meta,
                         int npack, const int* orbs, unsigned useI, unsigned useJ, double alpha,
                         int64_t npts, hipStream_t s) {
-  const dim3 grid((unsigned)((npts + 255) / 256));
   if (meta == nullptr) {
+    const dim3 grid((unsigned)((npts + 255) / 256));
     if (diag)
       hipLaunchKernelGGL((k_accumulate_full<TS, B, true>), grid, dim3(256), 0, s,
                          static_cast<const cx<TS>*>(S), phi, W, orbs, alpha, npts);
@@ -1302,13 +1302,13 @@ static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W, 
                          static_cast<const cx<TS>*>(S), phi, W, orbs, alpha, npts);
     return hipGetLastError();
   }
-  const dim3 grid_m((unsigned)((npts + kAccThreads - 1) / kAccThreads));
+  const dim3 grid((unsigned)((npts + kAccThreads - 1) / kAccThreads));
   if (diag)
-    hipLaunchKernelGGL((k_accumulate<TS, B, true>), grid_m, dim3(kAccThreads), 0, s,
+    hipLaunchKernelGGL((k_accumulate<TS, B, true>), grid, dim3(kAccThreads), 0, s,
                        static_cast<const cx<TS>*>(S), phi, W, meta, npack, orbs, useI, useJ,
                        alpha, npts);
   else
-    hipLaunchKernelGGL((k_accumulate<TS, B, false>), grid_m, dim3(kAccThreads), 0, s,
+    hipLaunchKernelGGL((k_accumulate<TS, B, false>), grid, dim3(kAccThreads), 0, s,
                        static_cast<const cx<TS>*>(S), phi, W, meta, npack, orbs, useI, useJ,
                        alpha, npts);
   return hipGetLastError();

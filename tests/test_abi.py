@@ -84,6 +84,7 @@ def test_supported_grids_plan_and_workspace(n, prec):
     assert lib.ace_plan_set_tiling(h, 8, 4, 0) == 0
     assert lib.ace_workspace_bytes(h) < ws
     assert lib.ace_plan_set_tiling(h, 12, 0, 0) == _lib.ACE_ERR_ARG
+    assert lib.ace_plan_set_tiling(h, 32, 0, 0) == _lib.ACE_ERR_ARG
     # x-pass pencils: 8, 16 or 32 where they divide n
     for c in (8, 16, 32):
         want = 0 if n % c == 0 else _lib.ACE_ERR_ARG

@@ -103,6 +103,28 @@ def test_ragged_tiles_and_chunks(lib, block, chunk):
     assert abs(out["ex"][0] - ref["ex"]) < TOL * abs(ref["ex"])
 
 
+@pytest.mark.parametrize("block", [8, 16])
+def test_mask_clustered_tiles(lib, block):
+    """45 orbitals, a sparse random mask: the kept pairs are re-blocked into
+    clusters, tiles are partial, some rows hold a single pair."""
+    _say("mask clusters n=24 orbitals=45 block", block)
+    spec = synth.SystemSpec("mc", 13.0, 24, 45, "random", 0, (1.0, 1.4), 0.25, 14)
+    s = synth.build_system(spec)
+    k = spec.n_orb
+    rng = np.random.default_rng(5)
+    mask = np.triu(rng.random((k, k)) < 0.3)
+    np.fill_diagonal(mask, rng.random(k) < 0.8)
+    ref = O.apply_vx(s.phi, spec.cell, spec.alpha, pair_mask=mask, workers=8)
+    for four_pass in (False, True):
+        plan = lib.Plan(spec.n, (spec.L,) * 3, k, "fp64", spec.alpha)
+        plan.set_tiling(block)
+        plan.set_schedule(four_pass)
+        out = lib.ace_build(plan, _dev(s.phi), pair_mask=mask)
+        import torch
+        torch.cuda.synchronize()
+        assert O.rel_err(_host(out["W"]), ref) < TOL
+
+
 def test_mask_parity_and_shard_sum(lib):
     """Screened pairs match the oracle; disjoint masks sum to the full W
     (the group sum over pair subsets that CP groups rely on)."""
