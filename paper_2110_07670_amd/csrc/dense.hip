@@ -252,99 +252,172 @@ hipError_t launch_gemm_ab(const double* A, const double* B, int m, int k, int64_
 }
 
 // ------------------------------------------------------------------ Cholesky and L^{-1}
-// One workgroup of 1024 threads.  The matrix lives in LDS when n <= 128 and
-// in the Linv output buffer otherwise.
-//  1. A = -M (lower triangle read).
-//  2. Right-looking Cholesky: pivot d = A[j][j]; a non-positive (or NaN)
-//     pivot stops with info = j + 1; L[j][j] = sqrt(d); scale the column;
-//     update the trailing lower triangle.
-//  3. L -> global.
-//  4. In-place inverse, columns from the last: with X = L^{-1} already in the
-//     trailing block, X[j][j] = 1 / L[j][j] and
-//     X[i][j] = -X[j][j] sum_{k=j+1..i} X[i][k] L[k][j]  (i > j);
-//     eight threads share each dot product (fixed-order shuffle sum).
-constexpr int kCholLdsN = 128;
+// -M = L L^T (lower, positive diagonal), then X = L^{-1}, in blocks of 32
+// columns (a partial last block when 32 does not divide n).
+//
+// k_chol_left: one workgroup of 1024 threads, left-looking, L built in place
+// in the L buffer (at these sizes it stays in the CU's caches).  Block column
+// J (columns j0 .. j0 + w - 1):
+//   1. the finished columns 0 .. j0-1 of its rows are staged in LDS,
+//      transposed: lj[k][c] = L[j0 + c][k];
+//   2. every row i >= j0: A[i][j0 + c] -= sum_{k < j0} L[i][k] lj[k][c]
+//      (thread = (row, c), k in increasing order);
+//   3. the diagonal block is factored in LDS, unblocked; a non-positive (or
+//      NaN) pivot stops the factorisation with info = column + 1;
+//   4. the rows below it are solved against it, L[i][J] = A[i][J] D^{-T}
+//      (one thread per row, the row in registers).
+// k_tri_inv: one workgroup per block column J of X; forward block
+// substitution down the row blocks I >= J with the block column in LDS:
+//   X[I][J] = D_I^{-1} (delta - sum_{J <= K < I} L[I][K] X[K][J]),
+// the triangular solve by one thread per column with the column in
+// registers.  Both are skipped after a failed factorisation (X undefined).
+constexpr int kCholNB = 32;
 constexpr int kCholMaxN = 512;
 
-template <bool LDS>
-__global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ M, int n,
-                                                   double* __restrict__ L,
-                                                   double* __restrict__ Linv,
-                                                   int* __restrict__ info) {
-  __shared__ double smat[LDS ? kCholLdsN * (kCholLdsN + 1) : 1];
-  __shared__ double col[kCholMaxN];
+__global__ __launch_bounds__(1024) void k_chol_left(const double* __restrict__ M, int n,
+                                                    double* __restrict__ L,
+                                                    int* __restrict__ info) {
+  __shared__ double lj[kCholMaxN - kCholNB][kCholNB];
+  __shared__ double dblk[kCholNB][kCholNB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
-  const int P = LDS ? n + 1 : n;
-  double* A = LDS ? smat : Linv;
+  const int c = tid % kCholNB, il = tid / kCholNB;
   for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
     const int i = (int)(e / n), j = (int)(e % n);
-    A[(int64_t)i * P + j] = (j <= i) ? -M[e] : 0.0;
+    L[e] = (j <= i) ? -M[e] : 0.0;
   }
   if (tid == 0) bad = 0;
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const double d = A[(int64_t)j * P + j];
-    if (!(d > 0.0)) {
-      if (tid == 0) bad = j + 1;
-      break;
+  for (int j0 = 0; j0 < n; j0 += kCholNB) {
+    const int w = min(kCholNB, n - j0);
+    // 1. stage the block's rows of the finished columns
+    for (int e = tid; e < j0 * kCholNB; e += 1024) {
+      const int k = e / kCholNB, cc = e % kCholNB;
+      lj[k][cc] = cc < w ? L[(int64_t)(j0 + cc) * n + k] : 0.0;
     }
-    const double ljj = sqrt(d);
     __syncthreads();
-    if (tid == 0) A[(int64_t)j * P + j] = ljj;
-    for (int i = j + 1 + tid; i < n; i += 1024) A[(int64_t)i * P + j] /= ljj;
+    // 2. left-looking update of the block column
+    if (c < w) {
+      for (int i = j0 + il; i < n; i += 1024 / kCholNB) {
+        const double* __restrict__ li = L + (int64_t)i * n;
+        double s = li[j0 + c];
+#pragma unroll 8
+        for (int k = 0; k < j0; ++k) s -= li[k] * lj[k][c];
+        L[(int64_t)i * n + j0 + c] = s;
+      }
+    }
     __syncthreads();
-    const int rem = n - j - 1;
-    for (int64_t e = tid; e < (int64_t)rem * rem; e += 1024) {
-      const int ii = (int)(e / rem), kk = (int)(e % rem);
-      if (kk > ii) continue;
-      const int i = j + 1 + ii, k = j + 1 + kk;
-      A[(int64_t)i * P + k] -= A[(int64_t)i * P + j] * A[(int64_t)k * P + j];
+    // 3. the diagonal block, factored in LDS
+    for (int e = tid; e < w * w; e += 1024) {
+      const int r = e / w, cc = e % w;
+      dblk[r][cc] = L[(int64_t)(j0 + r) * n + j0 + cc];
+    }
+    __syncthreads();
+    for (int j = 0; j < w; ++j) {
+      const double d = dblk[j][j];
+      if (!(d > 0.0)) {
+        if (tid == 0) bad = j0 + j + 1;
+        break;
+      }
+      const double ljj = sqrt(d);
+      __syncthreads();
+      if (tid == 0) dblk[j][j] = ljj;
+      if (tid > j && tid < w) dblk[tid][j] /= ljj;
+      __syncthreads();
+      const int rem = w - j - 1;
+      for (int e = tid; e < rem * rem; e += 1024) {
+        const int rr = e / rem, kk = e % rem;
+        if (kk <= rr) dblk[j + 1 + rr][j + 1 + kk] -= dblk[j + 1 + rr][j] * dblk[j + 1 + kk][j];
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (bad) break;
+    for (int e = tid; e < w * w; e += 1024) {
+      const int r = e / w, cc = e % w;
+      L[(int64_t)(j0 + r) * n + j0 + cc] = cc <= r ? dblk[r][cc] : 0.0;
+    }
+    // 4. rows below: forward substitution against the diagonal block (w = 32
+    // whenever rows remain below it)
+    const int i = j0 + kCholNB + tid;
+    if (w == kCholNB && i < n) {
+      double* __restrict__ li = L + (int64_t)i * n + j0;
+      double x[kCholNB];
+#pragma unroll
+      for (int cc = 0; cc < kCholNB; ++cc) x[cc] = li[cc];
+#pragma unroll
+      for (int cc = 0; cc < kCholNB; ++cc) {
+#pragma unroll
+        for (int k = 0; k < cc; ++k) x[cc] -= x[k] * dblk[cc][k];
+        x[cc] /= dblk[cc][cc];
+      }
+#pragma unroll
+      for (int cc = 0; cc < kCholNB; ++cc) li[cc] = x[cc];
     }
     __syncthreads();
   }
   __syncthreads();
-  const int failed = bad;
-  if (tid == 0) *info = failed;
-  if (failed) return;
-  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    L[e] = (j <= i) ? A[(int64_t)i * P + j] : 0.0;
-  }
-  __syncthreads();
-  const int g = tid & 7, row0 = tid >> 3;  // 128 row slots, 8 threads each
-  for (int j = n - 1; j >= 0; --j) {
-    for (int k = j + 1 + tid; k < n; k += 1024) col[k] = A[(int64_t)k * P + j];
-    __syncthreads();
-    const double djj = 1.0 / A[(int64_t)j * P + j];
-    for (int i0 = j + 1; i0 < n; i0 += 128) {
-      const int i = i0 + row0;
-      double s = 0.0;
-      if (i < n)
-        for (int k = j + 1 + g; k <= i; k += 8) s += A[(int64_t)i * P + k] * col[k];
-      s += __shfl_xor(s, 1, 64);
-      s += __shfl_xor(s, 2, 64);
-      s += __shfl_xor(s, 4, 64);
-      if (i < n && g == 0) A[(int64_t)i * P + j] = -djj * s;
+  if (tid == 0) *info = bad;
+}
+
+__global__ __launch_bounds__(1024) void k_tri_inv(const double* __restrict__ L, int n,
+                                                  double* __restrict__ X,
+                                                  const int* __restrict__ info) {
+  __shared__ double xs[kCholMaxN][kCholNB];  // rows j0 .. n-1 of the block column
+  __shared__ double dblk[kCholNB][kCholNB + 1];
+  if (*info != 0) return;
+  const int j0 = blockIdx.x * kCholNB;
+  const int w = min(kCholNB, n - j0);
+  const int tid = threadIdx.x, c = tid % kCholNB, il = tid / kCholNB;
+  for (int i0 = j0; i0 < n; i0 += kCholNB) {
+    const int h = min(kCholNB, n - i0);
+    // right-hand sides of row block I
+    if (il < h && c < w) {
+      const int i = i0 + il;
+      const double* __restrict__ li = L + (int64_t)i * n;
+      double s = (i == j0 + c) ? 1.0 : 0.0;
+#pragma unroll 8
+      for (int k = j0; k < i0; ++k) s -= li[k] * xs[k - j0][c];
+      xs[i - j0][c] = s;
+    }
+    for (int e = tid; e < h * h; e += 1024) {
+      const int r = e / h, cc = e % h;
+      dblk[r][cc] = L[(int64_t)(i0 + r) * n + i0 + cc];
     }
     __syncthreads();
-    if (tid == 0) A[(int64_t)j * P + j] = djj;
+    // X[I][J] = D_I^{-1} (right-hand sides): one thread per column
+    if (tid < w) {
+      double x[kCholNB];
+#pragma unroll
+      for (int r = 0; r < kCholNB; ++r) x[r] = r < h ? xs[i0 - j0 + r][tid] : 0.0;
+#pragma unroll
+      for (int r = 0; r < kCholNB; ++r) {
+        if (r < h) {
+#pragma unroll
+          for (int k = 0; k < r; ++k) x[r] -= dblk[r][k] * x[k];
+          x[r] /= dblk[r][r];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kCholNB; ++r)
+        if (r < h) xs[i0 - j0 + r][tid] = x[r];
+    }
     __syncthreads();
   }
-  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    if (LDS) Linv[e] = (j <= i) ? A[(int64_t)i * P + j] : 0.0;
-    else if (j > i) Linv[e] = 0.0;
+  for (int e = tid; e < n * kCholNB; e += 1024) {
+    const int i = e / kCholNB, cc = e % kCholNB;
+    if (cc >= w) continue;
+    const int col = j0 + cc;
+    X[(int64_t)i * n + col] = (i >= col) ? xs[i - j0][cc] : 0.0;
   }
 }
 
 hipError_t launch_cholesky_inv(const double* M, int n, double* L, double* Linv, int* info,
                                hipStream_t s) {
-  if (n > kCholMaxN) return hipErrorInvalidValue;
-  if (n <= kCholLdsN)
-    hipLaunchKernelGGL((k_chol_inv<true>), dim3(1), dim3(1024), 0, s, M, n, L, Linv, info);
-  else
-    hipLaunchKernelGGL((k_chol_inv<false>), dim3(1), dim3(1024), 0, s, M, n, L, Linv, info);
+  if (n > kCholMaxN || n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol_left, dim3(1), dim3(1024), 0, s, M, n, L, info);
+  hipLaunchKernelGGL(k_tri_inv, dim3((n + kCholNB - 1) / kCholNB), dim3(1024), 0, s, L, n, Linv,
+                     info);
   return hipGetLastError();
 }
 

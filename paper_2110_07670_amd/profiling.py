@@ -24,7 +24,8 @@ STAGE_OF = [
     ("k_plane_fwd", "yz_fwd"), ("k_rows_fwd", "yz_fwd"), ("k_plane_inv", "yz_inv"),
     ("k_rows_inv", "yz_inv"), ("k_accumulate", "w_accumulate"), ("k_zinv_acc", "w_accumulate"),
     ("k_plane_mid", "x_poisson"), ("k_gemm_abt", "abt_product"),
-    ("k_reduce_splits", "abt_product"), ("k_gemm_ab", "ab_product"), ("k_chol_inv", "cholesky_inv"),
+    ("k_reduce_splits", "abt_product"), ("k_gemm_ab", "ab_product"), ("k_chol_left", "cholesky_inv"),
+    ("k_tri_inv", "cholesky_inv"),
 ]
 
 
