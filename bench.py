@@ -508,12 +508,15 @@ def main():
             stages[name]["alg_GBps"] = ab / (stages[name]["ms_per_step"] * 1e-3) / 1e9
             stages[name]["alg_bytes_per_launch"] = ab / stages[name]["launches_per_step"]
             stages[name]["avg_launch_ms"] = launch_ms
-    if "m_product" in stages:
-        fl = 2.0 * spec.n_orb ** 2 * npts
-        stages["m_product"]["TFLOPs"] = fl / (stages["m_product"]["ms_per_step"] * 1e-3) / 1e12
-    if "xi_product" in stages:
-        fl = 2.0 * spec.n_orb ** 2 * npts
-        stages["xi_product"]["TFLOPs"] = fl / (stages["xi_product"]["ms_per_step"] * 1e-3) / 1e12
+    # FP64 MFMA products: M = dV Phi^T W and xi = W L^-T (2 n^2 N flops each),
+    # the apply (dV xi^T psi, then -xi C: 4 n n_vec N flops, n_vec = n here)
+    for name, fl in (("m_product", 2.0 * spec.n_orb ** 2 * npts),
+                     ("xi_product", 2.0 * spec.n_orb ** 2 * npts),
+                     ("apply_products", 4.0 * spec.n_orb ** 2 * npts)):
+        if name in stages:
+            tf = fl / (stages[name]["ms_per_step"] * 1e-3) / 1e12
+            stages[name]["TFLOPs"] = tf
+            stages[name]["mfma_frac"] = tf / FP64_MFMA_PEAK_TFLOPS
     dom = max((s for s in mem_stages if s in stages), key=lambda s: stages[s]["ms_per_step"])
     d = stages[dom]
     achieved = d["alg_bytes_per_launch"] / (d["avg_launch_ms"] * 1e-3) / 1e9
