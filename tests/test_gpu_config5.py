@@ -1,0 +1,138 @@
+"""Config 5 (128 waters at half liquid density, 512 orbitals, 160^3, FP32 bulk),
+at full size in the launch configuration bench.py times, against the FP64
+oracle's committed reference (tests/golden/make_reference.py: E_x from all
+131,328 pair energies, three M rows from oracle W rows, the pair energies
+themselves):
+
+- the all-pairs build: E_x, M rows, one W row and its ACE apply;
+- the screened builds (overlap screen with the paper's Table 3 cut, learned
+  MLP screen): E_x against the oracle's all-pairs E_x (the stated
+  1e-6 Ha per atom), E_x against the oracle's sum over the same kept pairs
+  (isolates the FP32 error of the masked path), and one W row against the
+  oracle's row restricted to the kept pairs (Eq. (2) over the mask)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ace_oracle as O
+from oracle import timing
+from paper_2110_07670_amd import screening, synth
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+REF = os.path.join(HERE, "golden", "reference_config5.json")
+PAIR_E = os.path.join(HERE, "golden", "pair_energies_config5.npz")
+ROW = 255
+RHO_CUT = 2e-3  # the paper's Table 3 cut for the largest (128-molecule) system
+TOL_EX_PER_ATOM = 1e-6
+TOL_ARRAYS = 1e-5  # FP32 transforms: relative, normwise, per result
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not os.path.exists(REF):
+        pytest.skip("no committed oracle reference for config 5")
+    ref = json.load(open(REF))
+    e_pairs = np.load(PAIR_E)["e"]
+    spec = synth.config(5)
+    s = synth.build_system(spec)
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    from make_reference import fingerprint_matches
+    assert fingerprint_matches(s.phi, ref["phi_fingerprint"]), "generator drift: regenerate"
+    # the oracle's process pool forks before this process initialises the GPU
+    w_ref = timing.apply_vx_rows_parallel(s.phi, spec.cell, spec.alpha, [ROW],
+                                          timing.default_processes())[ROW]
+    import torch
+    from paper_2110_07670_amd import _lib
+    assert torch.cuda.is_available()
+    phi = torch.from_numpy(s.phi).to("cuda:0")
+    plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, "fp32", spec.alpha)
+    return dict(spec=spec, s=s, ref=ref, e_pairs=e_pairs, w_ref=w_ref, lib=_lib, phi=phi,
+                plan=plan)
+
+
+def _masked_row_oracle(phi, cell, alpha, i, mask):
+    """W_i = -alpha sum over kept j of v_ij phi_j (Eq. (2) restricted to the kept pairs)."""
+    K = O.coulomb_kernel(phi.shape[1:], cell)
+    w = np.zeros_like(phi[i])
+    for j in range(phi.shape[0]):
+        if mask[min(i, j), max(i, j)]:
+            w -= alpha * O.pair_potential(phi[i] * phi[j], K) * phi[j]
+    return w
+
+
+def _build(st, mask=None):
+    import torch
+    lib, plan, phi = st["lib"], st["plan"], st["phi"]
+    out = lib.ace_build(plan, phi, pair_mask=mask)
+    back = lib.ace_apply(plan, out["xi"], phi[ROW:ROW + 1].contiguous())
+    torch.cuda.synchronize()
+    res = {"info": int(out["info"].item()), "ex": float(out["ex"].item()),
+           "W_row": out["W"][ROW].cpu().numpy(), "M": out["M"].cpu().numpy(),
+           "back": back.cpu().numpy()[0]}
+    del out
+    return res
+
+
+def test_config5_fp32_all_pairs(setup):
+    _say("config5 fp32 n=160 orbitals=512 all pairs")
+    st = setup
+    r = _build(st)
+    spec, ref = st["spec"], st["ref"]
+    ex_err = abs(r["ex"] - ref["ex"]) / spec.n_atoms
+    m_err = max(O.rel_err(r["M"][int(i)], np.array(v)) for i, v in ref["M_rows"].items())
+    w_err = O.rel_err(r["W_row"], st["w_ref"])
+    a_err = O.rel_err(r["back"], st["w_ref"])
+    print("config5 all pairs: E_x %.12f (oracle %.12f), %.2e Ha/atom; M rows %.2e; "
+          "W row %.2e; ACE row %.2e" % (r["ex"], ref["ex"], ex_err, m_err, w_err, a_err),
+          flush=True)
+    assert r["info"] == 0
+    assert ex_err < TOL_EX_PER_ATOM
+    assert m_err < TOL_ARRAYS and w_err < TOL_ARRAYS and a_err < TOL_ARRAYS
+
+
+def _check_screened(st, mask, label):
+    spec, ref, e = st["spec"], st["ref"], st["e_pairs"]
+    r = _build(st, mask)
+    kept = np.triu(mask)
+    ex_masked_oracle = float(e[kept].sum())
+    err_total = abs(r["ex"] - ref["ex"]) / spec.n_atoms
+    err_fp32 = abs(r["ex"] - ex_masked_oracle) / spec.n_atoms
+    skipped = abs(ref["ex"] - ex_masked_oracle) / spec.n_atoms
+    w_mask = _masked_row_oracle(st["s"].phi, spec.cell, spec.alpha, ROW, mask)
+    w_err = O.rel_err(r["W_row"], w_mask)
+    print("config5 %s screen: %d of %d pairs kept; E_x %.12f; error vs oracle all pairs "
+          "%.2e Ha/atom (skipped pairs %.2e, FP32 path %.2e); masked W row %.2e"
+          % (label, int(kept.sum()), spec.n_pairs, r["ex"], err_total, skipped, err_fp32,
+             w_err), flush=True)
+    assert r["info"] == 0
+    assert err_total < TOL_EX_PER_ATOM
+    assert err_fp32 < TOL_EX_PER_ATOM
+    assert w_err < TOL_ARRAYS
+
+
+def test_config5_overlap_screen(setup):
+    _say("config5 fp32 overlap screen rho_cut=%g" % RHO_CUT)
+    st = setup
+    S = st["lib"].overlap_integrals(st["plan"], st["phi"]).cpu().numpy()
+    _check_screened(st, screening.overlap_mask(S, RHO_CUT), "overlap")
+
+
+def test_config5_mlp_screen(setup):
+    _say("config5 fp32 learned MLP screen")
+    import torch
+    st = setup
+    X, y = screening.training_data()
+    params = screening.train_pair_mlp(X, y)
+    wts = torch.from_numpy(screening.weights_to_array(params)).to("cuda:0")
+    _, feat = st["lib"].wannier(st["plan"], st["phi"])
+    pred = st["lib"].mlp_screen(st["plan"], feat, wts).cpu().numpy()
+    mask = screening.mask_by_budget(pred, TOL_EX_PER_ATOM * st["spec"].n_atoms)
+    _check_screened(st, mask, "mlp")
