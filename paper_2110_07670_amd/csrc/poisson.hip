@@ -198,17 +198,18 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
       for (int t = 0; t < N2; ++t) lds[y * P + t + N2 * k1] = v[t];
     }
     lds_barrier();
-    // y step 1: tasks (pz, t2)
+    // y step 1: tasks (pz, u2), pz fastest (LDS only: consecutive threads on
+    // consecutive pz keep the column accesses of the odd-pitch rows apart)
     for (int task = tid; task < N * N2; task += NT) {
-      const int pz = task / N2;
+      const int pz = task % N, u2 = task / N;
       cx<T> v[N1];
 #pragma unroll
-      for (int j1 = 0; j1 < N1; ++j1) v[j1] = lds[(t2 + N2 * j1) * P + pz];
+      for (int j1 = 0; j1 < N1; ++j1) v[j1] = lds[(u2 + N2 * j1) * P + pz];
       dft<N1, false>(v);
 #pragma unroll
-      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[k1 * N2 + t2]);
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[k1 * N2 + u2]);
 #pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * P + pz] = v[k1];
+      for (int k1 = 0; k1 < N1; ++k1) lds[(u2 + N2 * k1) * P + pz] = v[k1];
     }
     const int next = item + gridDim.x;
     __builtin_amdgcn_sched_barrier(0);  // keep the prefetch below the y-step-1 work
