@@ -567,9 +567,14 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
       }
     }
     lds_barrier();
-    // inverse z step 1 to natural z: tasks (t2, c, m)
+    // inverse z step 1 to natural z: tasks (t2, c, m), t2 fastest; in the
+    // plane form then m (the row offset of a transform, 8 rows of the odd
+    // pitch, keeps the two halves of each 16 lanes on distinct banks), in the
+    // row form then c
     for (int task = tid; task < YC * N2 * ga; task += NT) {
-      const int t2 = task % N2, cc = (task / N2) % YC, m = task / (N2 * YC);
+      const int t2 = task % N2;
+      const int cc = ROWS ? (task / N2) % YC : task / (N2 * ga);
+      const int m = ROWS ? task / (N2 * YC) : (task / N2) % ga;
       cx<T> v[N1];
 #pragma unroll
       for (int k1 = 0; k1 < N1; ++k1) {
