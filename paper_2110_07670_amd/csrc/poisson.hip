@@ -137,6 +137,15 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
   for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];  // stw[k1 N2 + t2] = w^(t2 k1)
   __syncthreads();
 
+  // row of z-step-1 task group g: with eight lanes per row, the two halves of
+  // each 16 lanes take rows 8 apart (offset 8 on the odd pitch: distinct
+  // banks) instead of adjacent rows; a permutation within blocks of 16 rows
+  auto zrow = [](int g) __attribute__((always_inline)) {
+    if constexpr (N2 == 8 && N % 16 == 0)
+      return (g & ~15) | ((g & 1) << 3) | ((g >> 1) & 7);
+    else
+      return g;
+  };
   // phi_a, phi_b, phi_d of one item at this thread's z-step-1 elements
   T fa[Q1][N1], fb[Q1][N1], fd[Q1][N1];
   auto fetch = [&](int it) __attribute__((always_inline)) {
@@ -150,7 +159,7 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
 #pragma unroll
     for (int q = 0; q < Q1; ++q) {
       const int task = tid + q * NT;
-      const int y = (task < N * N2 ? task : 0) / N2;
+      const int y = zrow((task < N * N2 ? task : 0) / N2);
 #pragma unroll
       for (int j1 = 0; j1 < N1; ++j1) {
         const int off = y * N + t2 + N2 * j1;
@@ -173,7 +182,7 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
     for (int q = 0; q < Q1; ++q) {
       const int task = tid + q * NT;
       if (task < N * N2) {
-        const int y = task / N2;
+        const int y = zrow(task / N2);
         cx<T> v[N1];
 #pragma unroll
         for (int j1 = 0; j1 < N1; ++j1)
@@ -406,9 +415,12 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
     for (int t = 0; t < N2; ++t) lds[x * P + t + N2 * k1] = v[t];
   }
   __syncthreads();
-  // y inverse step 1 -> global, natural y: tasks (x, t2), t2 fastest
+  // y inverse step 1 -> global, natural y: tasks (x, t2), t2 fastest; with
+  // eight lanes per row the two halves of each 16 lanes take rows 8 apart
+  // (distinct banks on the odd pitch), a permutation within blocks of 16 rows
   for (int task = tid; task < N * N2; task += NT) {
-    const int t2 = task % N2, x = task / N2;
+    const int t2 = task % N2, g = task / N2;
+    const int x = (N2 == 8 && N % 16 == 0) ? ((g & ~15) | ((g & 1) << 3) | ((g >> 1) & 7)) : g;
     cx<T> v[N1];
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[x * P + t2 + N2 * k1], stw[k1 * N2 + t2]);
