@@ -664,7 +664,8 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
 
 // ------------------------------------------------------------------ z rows (fallback)
 // Forward: pair density + z transform of kRowsPerBlock consecutive rows,
-// written in position order.  Twiddles in LDS as stw[k1 N2 + t2].
+// written in position order with streaming stores (the y pass reads them
+// once).  Twiddles in LDS as stw[k1 N2 + t2].
 template <typename T, int N>
 __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
     const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
@@ -712,7 +713,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
   }
   __syncthreads();
   cx<T>* __restrict__ out = S + (int64_t)p * npts + row0;
-  for (int e = tid; e < R * N; e += NT) out[e] = lds[(e / N) * P + (e % N)];
+  for (int e = tid; e < R * N; e += NT) st_stream(&out[e], lds[(e / N) * P + (e % N)]);
 }
 
 // Inverse z transform of position-ordered rows to natural order.
