@@ -520,11 +520,21 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
     m = task / (YC * N1);
   };
 
+  // W is read and written with streaming accesses: the rows of a W update
+  // are far apart in time, and kept out of the caches they leave room for
+  // the orbital rows that the next tile's forward pass reads again (measured:
+  // forward pass 19.9 to 17.5 ms per build at 96^3).  The FP64 orbitals are
+  // streamed too when the transforms are FP32 (the forward pass then reads
+  // an FP32 copy).
+  auto ld_orb = [&](int64_t i) __attribute__((always_inline)) {
+    if constexpr (sizeof(T) == 4) return __builtin_nontemporal_load(&phi[i]);
+    else return phi[i];
+  };
   // off-diagonal: ph = phi_J, acc = W_J sums; diagonal: the tile's B orbitals
   double ph[B], acc[B];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    ph[b] = phi[(int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r];
+    ph[b] = ld_orb((int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r);
     acc[b] = 0.0;
   }
   __syncthreads();
@@ -566,8 +576,8 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
     const int64_t oa = (int64_t)orbs[a] * npts + r;
     double phA = 0.0, wA = 0.0;
     if constexpr (!DIAG) {
-      phA = phi[oa];
-      wA = W[oa];
+      phA = ld_orb(oa);
+      wA = __builtin_nontemporal_load(&W[oa]);
     }
     if constexpr (PF) {
 #pragma unroll
@@ -631,7 +641,7 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
         acc[2 * m] += v0 * phA;
         acc[2 * m + 1] += v1 * phA;
       }
-      W[oa] = wA - alpha * accA;
+      __builtin_nontemporal_store(wA - alpha * accA, &W[oa]);
     } else {
       // row a at compile time, so every register index is static
       sfor<0, B>([&](auto ac) {
@@ -658,7 +668,7 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int64_t ob = (int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r;
-    W[ob] -= alpha * acc[b];
+    __builtin_nontemporal_store(__builtin_nontemporal_load(&W[ob]) - alpha * acc[b], &W[ob]);
   }
 }
 
