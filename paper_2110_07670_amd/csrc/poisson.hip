@@ -900,6 +900,17 @@ __global__ __launch_bounds__((line_threads<N, C>())) void k_lines(
 constexpr int kAccThreads = 128;
 constexpr int kAccAhead = 8;  // transforms whose loads are issued ahead
 
+// W -= d with streaming accesses (as in the fused pass: W rows are touched
+// far apart in time); FP64 orbitals streamed under FP32 transforms
+__device__ __forceinline__ void w_sub(double* p, double d) {
+  __builtin_nontemporal_store(__builtin_nontemporal_load(p) - d, p);
+}
+template <typename TS>
+__device__ __forceinline__ double ld_orb_acc(const double* p) {
+  if constexpr (sizeof(TS) == 4) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 template <typename TS, int B, bool DIAG>
 __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W,
@@ -914,7 +925,7 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
   const int* side = DIAG ? orbs : orbs + B;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    sph[b][t] = ((use >> b) & 1u) ? phi[(int64_t)side[b] * npts + r] : 0.0;
+    sph[b][t] = ((use >> b) & 1u) ? ld_orb_acc<TS>(&phi[(int64_t)side[b] * npts + r]) : 0.0;
     sacc[b][t] = 0.0;
   }
   int cur = -1;  // current row a
@@ -944,14 +955,14 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
       if (a != cur) {
         if (cur >= 0) {
           if constexpr (DIAG) sacc[cur][t] = accA;
-          else W[(int64_t)orbs[cur] * npts + r] -= alpha * accA;
+          else w_sub(&W[(int64_t)orbs[cur] * npts + r], alpha * accA);
         }
         cur = a;
         if constexpr (DIAG) {
           phA = sph[a][t];
           accA = sacc[a][t];  // contributions of earlier rows, where a was the column
         } else {
-          phA = phi[(int64_t)orbs[a] * npts + r];
+          phA = ld_orb_acc<TS>(&phi[(int64_t)orbs[a] * npts + r]);
           accA = 0.0;
         }
       }
@@ -961,11 +972,11 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
   }
   if (cur >= 0) {
     if constexpr (DIAG) sacc[cur][t] = accA;
-    else W[(int64_t)orbs[cur] * npts + r] -= alpha * accA;
+    else w_sub(&W[(int64_t)orbs[cur] * npts + r], alpha * accA);
   }
 #pragma unroll
   for (int b = 0; b < B; ++b)
-    if ((use >> b) & 1u) W[(int64_t)side[b] * npts + r] -= alpha * sacc[b][t];
+    if ((use >> b) & 1u) w_sub(&W[(int64_t)side[b] * npts + r], alpha * sacc[b][t]);
 }
 
 template <typename TS, int B, bool DIAG>
