@@ -512,7 +512,7 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
     {
       ProfScope ps(p, 3, s);
       if (fused) {
-        e = acex::launch_zinv_acc(g, B, t.diag, S, phi, W, t_orbs, p->alpha, s);
+        e = acex::launch_zinv_acc(g, B, t.diag, S, phi_bulk, W, t_orbs, p->alpha, s);
       } else {
         const bool full = t.bi == B && t.bj == B && t.complete;
         e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,

@@ -51,8 +51,9 @@ bool three_pass_ok(int n, int prec, int block);
 bool fused_rows_ok(int n, int prec, int block);
 hipError_t launch_inv_y(const GridArgs& g, void* S, int npack, hipStream_t s);
 hipError_t launch_mid(const GridArgs& g, void* S, int npack, hipStream_t s);
+// phi: the orbitals in the bulk precision (FP64, or the FP32 copy).
 hipError_t launch_zinv_acc(const GridArgs& g, int block, bool diag, const void* S,
-                           const double* phi, double* W, const int* orbs, double alpha,
+                           const void* phi, double* W, const int* orbs, double alpha,
                            hipStream_t s);
 // x transforms with the Coulomb multiply between forward and inverse, in place.
 hipError_t launch_poisson_x(const GridArgs& g, void* S, int npack, hipStream_t s);

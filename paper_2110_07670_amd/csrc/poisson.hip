@@ -473,7 +473,7 @@ constexpr bool zinv_ok() {
 // diagonal tiles: all B sums at the end.  Fixed order, no atomics.
 template <typename T, int N, int B, bool DIAG, bool ROWS>
 __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
-    const cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, const double* __restrict__ phi,
+    const cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, const T* __restrict__ phi,
     double* __restrict__ W, const int* __restrict__ orbs, double alpha, int64_t npts) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
   constexpr int NT = zinv_threads<T, N, ROWS>(), G = B / 2, YC = zinv_rows<T, ROWS>();
@@ -523,18 +523,15 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
   // W is read and written with streaming accesses: the rows of a W update
   // are far apart in time, and kept out of the caches they leave room for
   // the orbital rows that the next tile's forward pass reads again (measured:
-  // forward pass 19.9 to 17.5 ms per build at 96^3).  The FP64 orbitals are
-  // streamed too when the transforms are FP32 (the forward pass then reads
-  // an FP32 copy).
-  auto ld_orb = [&](int64_t i) __attribute__((always_inline)) {
-    if constexpr (sizeof(T) == 4) return __builtin_nontemporal_load(&phi[i]);
-    else return phi[i];
-  };
+  // forward pass 19.9 to 17.5 ms per build at 96^3).  The orbitals come in
+  // the bulk precision (with FP32 transforms, the FP32 copy the forward pass
+  // reads: half the bytes and registers; the products and sums stay FP64).
   // off-diagonal: ph = phi_J, acc = W_J sums; diagonal: the tile's B orbitals
-  double ph[B], acc[B];
+  T ph[B];
+  double acc[B];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    ph[b] = ld_orb((int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r);
+    ph[b] = phi[(int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r];
     acc[b] = 0.0;
   }
   __syncthreads();
@@ -574,9 +571,10 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
   for (int a = 0; a < B; ++a) {
     const int ga = DIAG ? (B - a + 1) / 2 : G;  // transforms in row a
     const int64_t oa = (int64_t)orbs[a] * npts + r;
-    double phA = 0.0, wA = 0.0;
+    T phA = T(0);
+    double wA = 0.0;
     if constexpr (!DIAG) {
-      phA = ld_orb(oa);
+      phA = phi[oa];
       wA = __builtin_nontemporal_load(&W[oa]);
     }
     if constexpr (PF) {
@@ -1147,25 +1145,25 @@ static hipError_t mid_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
 }
 
 template <typename T, int N, int B, bool ROWS>
-static hipError_t zinv_launch(const GridArgs& g, bool diag, const void* S, const double* phi,
+static hipError_t zinv_launch(const GridArgs& g, bool diag, const void* S, const void* phi,
                               double* W, const int* orbs, double alpha, hipStream_t s) {
   if constexpr (zinv_ok<T, N, B, ROWS>()) {
     const dim3 grid(N * (N / zinv_rows<T, ROWS>())), block(zinv_threads<T, N, ROWS>());
     if (diag)
       hipLaunchKernelGGL((k_zinv_acc<T, N, B, true, ROWS>), grid, block, 0, s,
-                         static_cast<const cx<T>*>(S), static_cast<const cx<T>*>(g.tw), phi, W,
-                         orbs, alpha, g.npts);
+                         static_cast<const cx<T>*>(S), static_cast<const cx<T>*>(g.tw),
+                         static_cast<const T*>(phi), W, orbs, alpha, g.npts);
     else
       hipLaunchKernelGGL((k_zinv_acc<T, N, B, false, ROWS>), grid, block, 0, s,
-                         static_cast<const cx<T>*>(S), static_cast<const cx<T>*>(g.tw), phi, W,
-                         orbs, alpha, g.npts);
+                         static_cast<const cx<T>*>(S), static_cast<const cx<T>*>(g.tw),
+                         static_cast<const T*>(phi), W, orbs, alpha, g.npts);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T, int N, int B>
-static hipError_t zinv_t(const GridArgs& g, bool diag, const void* S, const double* phi,
+static hipError_t zinv_t(const GridArgs& g, bool diag, const void* S, const void* phi,
                          double* W, const int* orbs, double alpha, hipStream_t s) {
   if constexpr (plane_ok<T, N>())
     return zinv_launch<T, N, B, false>(g, diag, S, phi, W, orbs, alpha, s);
@@ -1289,7 +1287,7 @@ hipError_t launch_mid(const GridArgs& g, void* S, int npack, hipStream_t s) {
 }
 
 hipError_t launch_zinv_acc(const GridArgs& g, int block, bool diag, const void* S,
-                           const double* phi, double* W, const int* orbs, double alpha,
+                           const void* phi, double* W, const int* orbs, double alpha,
                            hipStream_t s) {
   switch (g.n) {
 #define X(N)                                                                               \
