@@ -515,7 +515,7 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
         e = acex::launch_zinv_acc(g, B, t.diag, S, phi_bulk, W, t_orbs, p->alpha, s);
       } else {
         const bool full = t.bi == B && t.bj == B && t.complete;
-        e = acex::launch_accumulate(p->prec, B, t.diag, S, phi, W,
+        e = acex::launch_accumulate(p->prec, B, t.diag, S, phi_bulk, W,
                                     full ? nullptr : d_meta + t.pack0, t.npack, t_orbs, t.useI,
                                     t.useJ, p->alpha, p->npts, s);
       }

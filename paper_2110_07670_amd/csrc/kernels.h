@@ -70,7 +70,8 @@ hipError_t launch_inv_yz(const GridArgs& g, void* S, int npack, hipStream_t s);
 // meta == nullptr: a full unmasked B x B tile in the canonical a-major order.
 // orbs: the tile's 2B orbital indices (I list, then J list); useI / useJ:
 // local orbitals with at least one pair.
-hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const double* phi,
+// phi: the orbitals in the bulk precision (FP64, or the FP32 copy).
+hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const void* phi,
                              double* W, const int* meta, int npack, const int* orbs,
                              unsigned useI, unsigned useJ, double alpha, int64_t npts,
                              hipStream_t s);

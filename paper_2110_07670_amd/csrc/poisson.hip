@@ -899,22 +899,19 @@ constexpr int kAccThreads = 128;
 constexpr int kAccAhead = 8;  // transforms whose loads are issued ahead
 
 // W -= d with streaming accesses (as in the fused pass: W rows are touched
-// far apart in time); FP64 orbitals streamed under FP32 transforms
+// far apart in time).  The orbitals come in the bulk precision, as in the
+// fused pass.
 __device__ __forceinline__ void w_sub(double* p, double d) {
   __builtin_nontemporal_store(__builtin_nontemporal_load(p) - d, p);
-}
-template <typename TS>
-__device__ __forceinline__ double ld_orb_acc(const double* p) {
-  if constexpr (sizeof(TS) == 4) return __builtin_nontemporal_load(p);
-  else return *p;
 }
 
 template <typename TS, int B, bool DIAG>
 __global__ __launch_bounds__(kAccThreads) void k_accumulate(
-    const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W,
+    const cx<TS>* __restrict__ S, const TS* __restrict__ phi, double* __restrict__ W,
     const int* __restrict__ meta, int npack, const int* __restrict__ orbs, unsigned useI,
     unsigned useJ, double alpha, int64_t npts) {
-  __shared__ double sph[B][kAccThreads], sacc[B][kAccThreads];
+  __shared__ TS sph[B][kAccThreads];
+  __shared__ double sacc[B][kAccThreads];
   const int t = threadIdx.x;
   const int64_t r = (int64_t)blockIdx.x * kAccThreads + t;
   if (r >= npts) return;  // no barriers below
@@ -923,7 +920,7 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
   const int* side = DIAG ? orbs : orbs + B;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    sph[b][t] = ((use >> b) & 1u) ? ld_orb_acc<TS>(&phi[(int64_t)side[b] * npts + r]) : 0.0;
+    sph[b][t] = ((use >> b) & 1u) ? phi[(int64_t)side[b] * npts + r] : TS(0);
     sacc[b][t] = 0.0;
   }
   int cur = -1;  // current row a
@@ -960,7 +957,7 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
           phA = sph[a][t];
           accA = sacc[a][t];  // contributions of earlier rows, where a was the column
         } else {
-          phA = ld_orb_acc<TS>(&phi[(int64_t)orbs[a] * npts + r]);
+          phA = phi[(int64_t)orbs[a] * npts + r];
           accA = 0.0;
         }
       }
@@ -979,13 +976,13 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
 
 template <typename TS, int B, bool DIAG>
 __global__ __launch_bounds__(256) void k_accumulate_full(
-    const cx<TS>* __restrict__ S, const double* __restrict__ phi, double* __restrict__ W,
+    const cx<TS>* __restrict__ S, const TS* __restrict__ phi, double* __restrict__ W,
     const int* __restrict__ orbs, double alpha, int64_t npts) {
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (r >= npts) return;
   static_assert(DIAG || B % 2 == 0, "off-diagonal rows pack evenly");
-  double phI[B], accI[B];
-  double phJ[DIAG ? 1 : B], accJ[DIAG ? 1 : B];
+  TS phI[B], phJ[DIAG ? 1 : B];
+  double accI[B], accJ[DIAG ? 1 : B];
 #pragma unroll
   for (int a = 0; a < B; ++a) {
     phI[a] = phi[(int64_t)orbs[a] * npts + r];
@@ -1345,9 +1342,10 @@ hipError_t launch_energy_x(const GridArgs& g, const void* S, int npack, double* 
 }
 
 template <typename TS, int B>
-static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W, const int* meta,
+static hipError_t acc_t(bool diag, const void* S, const void* phi_v, double* W, const int* meta,
                         int npack, const int* orbs, unsigned useI, unsigned useJ, double alpha,
                         int64_t npts, hipStream_t s) {
+  const TS* phi = static_cast<const TS*>(phi_v);
   if (meta == nullptr) {
     const dim3 grid((unsigned)((npts + 255) / 256));
     if (diag)
@@ -1370,7 +1368,7 @@ static hipError_t acc_t(bool diag, const void* S, const double* phi, double* W, 
   return hipGetLastError();
 }
 
-hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const double* phi,
+hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, const void* phi,
                              double* W, const int* meta, int npack, const int* orbs,
                              unsigned useI, unsigned useJ, double alpha, int64_t npts,
                              hipStream_t s) {
