@@ -487,11 +487,12 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
   const int tid = threadIdx.x;
   const int bid = blockIdx.x;
   int x, y0;
-  if constexpr (!ROWS && YC * sizeof(cx<T>) < 128) {
-    // two workgroups share each 128-byte scratch segment: they run back to
-    // back on one XCD (workgroup b runs on XCD b mod 8), so the second finds
-    // the lines in L2
-    constexpr int H = 128 / (YC * int(sizeof(cx<T>)));  // workgroups per segment
+  // workgroups per 128-byte scratch segment (FP32: two)
+  constexpr int H = YC * int(sizeof(cx<T>)) < 128 ? 128 / (YC * int(sizeof(cx<T>))) : 1;
+  if constexpr (!ROWS && H > 1 && N % (H * YC) == 0) {
+    // the H workgroups sharing a segment run back to back on one XCD
+    // (workgroup b runs on XCD b mod 8), so the later ones find the lines in
+    // L2; only where whole segments tile the y rows (else the plain order)
     const int g = bid >> 3, xcd = bid & 7;
     const int seg = (g / H) * 8 + xcd;
     y0 = (seg % (N / (H * YC))) * (H * YC) + (g % H) * YC;

@@ -104,6 +104,24 @@ def test_three_pass_fp32_matches_four_pass(lib, n):
     assert abs(three["ex"][0] - ref["ex"][0]) < 1e-6 * abs(ref["ex"][0])
 
 
+@pytest.mark.parametrize("n", [16, 24, 32, 40, 48, 64, 80, 96, 120, 128])
+def test_three_pass_every_plane_grid_fp32_against_oracle(lib, n):
+    """FP32 bulk on every grid whose FP32 plane fits LDS (the three-pass
+    schedule), 16 orbitals in blocks of 8 (three full tiles): W and E_x within
+    the FP32 bounds of the FP64 oracle.  Covers the inverse-z workgroup order
+    on grids that whole 128-byte scratch segments do not tile (24, 40, 120)."""
+    _say("three-pass fp32 n=%d orbitals 16 block 8 vs oracle" % n)
+    spec = synth.SystemSpec("t3o", 0.11 * n + 5.0, n, 16, "random", 0, (1.0, 1.4), 0.25, 700 + n)
+    s = synth.build_system(spec)
+    ref = O.ace_build(s.phi, spec.cell, spec.alpha, workers=8)
+    p = lib.Plan(spec.n, (spec.L,) * 3, 16, "fp32", spec.alpha)
+    p.set_tiling(8)
+    out = _host(lib.ace_build(p, _dev(s.phi)))
+    assert out["info"][0] == 0
+    assert O.rel_err(out["W"], ref["W"]) < 1e-6
+    assert abs(out["ex"][0] - ref["ex"]) < 1e-6 * abs(ref["ex"])
+
+
 @pytest.mark.parametrize("n", [120, 144])
 def test_fused_rows_large_grids_fp64(lib, n):
     """Grids whose plane does not fit LDS: the large-grid schedule fuses the
