@@ -542,8 +542,9 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
   // so that they are in flight while it runs (the barriers order LDS only);
   // with FP64 ones the registers for that do not fit next to the W sums
   // (measured slower with the spills) and each row loads at its start, with
-  // streaming loads (4% faster at 96^3; the prefetched FP32 form measured
-  // slower with them).  With
+  // streaming loads in the plane form (4% faster at 96^3; the row form and
+  // the prefetched FP32 form measured slower with them: 42 to 77 ms per
+  // build at 120^3).  With
   // the prefetch the four-step twiddles are applied at the end of step 2,
   // which keeps step 1 light; without it, at the start of step 1.
   constexpr int T2MAX = YC * N1 * G;
@@ -599,7 +600,8 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
         const cx<T>* __restrict__ src = sx + (int64_t)(q0 + m) * npts + cc * CS;
         cx<T> v[N2];
 #pragma unroll
-        for (int t = 0; t < N2; ++t) v[t] = ld_stream(&src[(int64_t)(t + N2 * k1) * KS]);
+        for (int t = 0; t < N2; ++t)
+          v[t] = ROWS ? src[(int64_t)(t + N2 * k1) * KS] : ld_stream(&src[(int64_t)(t + N2 * k1) * KS]);
         dft<N2, true>(v);
 #pragma unroll
         for (int t = 0; t < N2; ++t) lds[(m * YC + cc) * P + t + N2 * k1] = v[t];
