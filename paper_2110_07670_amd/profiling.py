@@ -7,6 +7,8 @@ counters read for a plain 1 GiB device copy in the same process
 (bench.py --copy-calibration), whose true traffic is 1 GiB read + 1 GiB written.
 
 Usage: python -m paper_2110_07670_amd.profiling TRACE_DB FETCH_DB WRITE_DB OUT.md "COMMAND"
+       python -m paper_2110_07670_amd.profiling --trace-only TRACE_DB OUT.md "TITLE" "COMMAND"
+(the second form: kernel times per kernel and per stage from a trace alone)
 """
 from __future__ import annotations
 
@@ -112,7 +114,33 @@ def summarize(trace_db, fetch_db, write_db, out_md, command):
     return rec
 
 
+def summarize_trace(trace_db, out_md, title, command):
+    """Kernel-trace summary only (no counters): calls, average and total time
+    per kernel and the time per stage."""
+    stats = kernel_stats(trace_db)
+    lines = ["# rocprofv3 summary: %s" % title, "",
+             "Command (run from the repository root on one MI355X):", "", "```", command, "```",
+             "", "| kernel | stage | calls | avg us | total ms |", "|---|---|---|---|---|"]
+    per_stage = collections.OrderedDict()
+    for k, (calls, tot) in stats.items():
+        st = stage_of(k)
+        lines.append("| %s | %s | %d | %.1f | %.3f |" % (k[:70], st, calls, tot / calls / 1e3,
+                                                        tot / 1e6))
+        a = per_stage.setdefault(st, [0, 0.0])
+        a[0] += calls
+        a[1] += tot
+    lines += ["", "| stage | launches | total ms |", "|---|---|---|"]
+    for st, (calls, tot) in per_stage.items():
+        lines.append("| %s | %d | %.3f |" % (st, calls, tot / 1e6))
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return {st: tot / 1e6 for st, (_, tot) in per_stage.items()}
+
+
 if __name__ == "__main__":
-    if len(sys.argv) != 6:
+    if len(sys.argv) == 6 and sys.argv[1] == "--trace-only":
+        print(json.dumps(summarize_trace(*sys.argv[2:6]), indent=1))
+    elif len(sys.argv) == 6:
+        print(json.dumps(summarize(*sys.argv[1:6]), indent=1))
+    else:
         sys.exit(__doc__)
-    print(json.dumps(summarize(*sys.argv[1:6]), indent=1))
