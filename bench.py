@@ -421,12 +421,17 @@ def main():
                     help="four transform passes on every tile (ace_plan_set_schedule)")
     ap.add_argument("--no-tune", action="store_true",
                     help="--config 4 with the default launch shapes")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
+                    help="bulk precision (default: FP64 for configs 1-2 and SCDM, FP32 for "
+                         "configs 3-5, as the workloads are specified)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for counter calibration runs)")
     ap.add_argument("--screen", choices=["mlp", "overlap"], default=None,
                     help="measure a screened build against the all-pairs build instead")
     args = ap.parse_args()
+    if args.precision is None:
+        cfg = 5 if args.screen and args.config == 2 else args.config  # the screened default
+        args.precision = "fp32" if cfg in (3, 4, 5) and not args.scdm else "fp64"
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU: the ACE build here runs on a single MI355X "
                  "(--gpus %d requested; multi-GPU sharding is described, not built)" % args.gpus)
