@@ -22,10 +22,12 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
 
 // ------------------------------------------------------------------ C = A B^T, split K
 // Workgroup: 256 threads (4 waves in 2 x 2), output tile 128 x 128, each wave
-// 64 x 64 = 4 x 4 MFMA blocks.  K staged through LDS in slabs of KT; the next
-// slab is loaded into registers while the current one feeds the MFMAs.
+// 64 x 64 = 4 x 4 MFMA blocks.  K staged through two LDS buffers in slabs of
+// KT: while the MFMAs read one slab, the next one (loaded into registers
+// behind them) is stored into the other buffer, so each slab costs one
+// barrier.
 constexpr int kAbtTile = 128;
-constexpr int kAbtKT = 32;
+constexpr int kAbtKT = 16;
 constexpr int kAbtPitch = kAbtKT + 1;
 constexpr int kAbtPer = kAbtTile * kAbtKT / 256;  // elements per thread per operand
 
@@ -35,8 +37,8 @@ __global__ __launch_bounds__(256) void k_gemm_abt(const double* __restrict__ A,
                                                   bool abs_in, double* __restrict__ partial,
                                                   const int* __restrict__ skip) {
   if (skip && *skip != 0) return;
-  __shared__ double sA[kAbtTile * kAbtPitch];
-  __shared__ double sB[kAbtTile * kAbtPitch];
+  __shared__ double sA[2][kAbtTile * kAbtPitch];
+  __shared__ double sB[2][kAbtTile * kAbtPitch];
   const int tile = blockIdx.x;
   const int split = blockIdx.y;
   const int tm = tile / tiles_n, tn = tile % tiles_n;
@@ -69,32 +71,41 @@ __global__ __launch_bounds__(256) void k_gemm_abt(const double* __restrict__ A,
       rb[q] = abs_in ? fabs(vb) : vb;
     }
   };
-  if (kbeg < kend) fetch(kbeg);
-  for (int64_t k0 = kbeg; k0 < kend; k0 += kAbtKT) {
+  auto stage = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < kAbtPer; ++q) {
       const int e = tid + q * 256;
       const int r = e / kAbtKT, c = e % kAbtKT;
-      sA[r * kAbtPitch + c] = ra[q];
-      sB[r * kAbtPitch + c] = rb[q];
+      sA[buf][r * kAbtPitch + c] = ra[q];
+      sB[buf][r * kAbtPitch + c] = rb[q];
     }
-    __syncthreads();
-    if (k0 + kAbtKT < kend) fetch(k0 + kAbtKT);
+  };
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stage(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kAbtKT) {
+    const bool more = k0 + kAbtKT < kend;
+    if (more) fetch(k0 + kAbtKT);
 #pragma unroll
     for (int kk = 0; kk < kAbtKT; kk += 4) {
       double af[4], bf[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        af[i] = sA[(wm * 64 + i * 16 + (lane & 15)) * kAbtPitch + kk + (lane >> 4)];
+        af[i] = sA[buf][(wm * 64 + i * 16 + (lane & 15)) * kAbtPitch + kk + (lane >> 4)];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        bf[j] = sB[(wn * 64 + j * 16 + (lane & 15)) * kAbtPitch + kk + (lane >> 4)];
+        bf[j] = sB[buf][(wn * 64 + j * 16 + (lane & 15)) * kAbtPitch + kk + (lane >> 4)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(af[i], bf[j], acc[i][j]);
     }
+    if (more) stage(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   double* out = partial + (int64_t)split * m * n;
 #pragma unroll
