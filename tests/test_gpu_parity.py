@@ -125,6 +125,44 @@ def test_mask_clustered_tiles(lib, block):
         assert O.rel_err(_host(out["W"]), ref) < TOL
 
 
+def test_single_orbital(lib):
+    """One doubly occupied orbital: the 1 x 1 tile, E_X = -(11|11) (the paper's
+    Eq. (4) with a single pair), against the oracle."""
+    _say("single orbital n=24")
+    spec = synth.SystemSpec("one", 9.0, 24, 1, "random", 0, (1.0, 1.4), 0.25, 19)
+    s = synth.build_system(spec)
+    ref = O.ace_build(s.phi, spec.cell, spec.alpha, workers=4)
+    for precision, tol in (("fp64", TOL), ("fp32", 1e-6)):
+        plan, out = _build(lib, spec, s.phi, precision)
+        assert out["info"][0] == 0
+        assert O.rel_err(out["W"], ref["W"]) < tol
+        assert abs(out["ex"][0] - ref["ex"]) < tol * abs(ref["ex"])
+
+
+def test_empty_and_diagonal_masks(lib):
+    """No kept pair: W = 0 exactly, -M = 0 is not positive definite (info = 1),
+    E_x = 0; only the diagonal kept: W against the oracle's masked sum."""
+    _say("empty and diagonal-only masks n=24 orbitals=12")
+    import torch
+    spec = synth.SystemSpec("em", 10.0, 24, 12, "random", 0, (1.0, 1.4), 0.25, 23)
+    s = synth.build_system(spec)
+    k = spec.n_orb
+    plan = lib.Plan(spec.n, (spec.L,) * 3, k, "fp64", spec.alpha)
+    empty = np.zeros((k, k), bool)
+    out = lib.ace_build(plan, _dev(s.phi), pair_mask=empty)
+    torch.cuda.synchronize()
+    assert not np.any(_host(out["W"]))
+    assert int(_host(out["info"])[0]) == 1
+    assert _host(out["ex"])[0] == 0.0
+    ex, _ = lib.exx_energy(plan, _dev(s.phi), pair_mask=empty)
+    assert _host(ex)[0] == 0.0
+    diag = np.eye(k, dtype=bool)
+    ref = O.apply_vx(s.phi, spec.cell, spec.alpha, pair_mask=diag, workers=8)
+    out = lib.ace_build(plan, _dev(s.phi), pair_mask=diag)
+    torch.cuda.synchronize()
+    assert O.rel_err(_host(out["W"]), ref) < TOL
+
+
 def test_mask_parity_and_shard_sum(lib):
     """Screened pairs match the oracle; disjoint masks sum to the full W
     (the group sum over pair subsets that CP groups rely on)."""
