@@ -58,8 +58,9 @@ typedef struct ace_plan ace_plan;
 
 enum ace_precision {
   ACE_FP64 = 0, /* all stages in FP64 */
-  ACE_FP32 = 1  /* pair densities, transforms and Coulomb multiply in FP32;
-                   W accumulation, M, Cholesky, xi and E_x stay in FP64 */
+  ACE_FP32 = 1  /* pair densities, transforms and Coulomb multiply in FP32
+                   (from an FP32 copy of phi, which the W update also reads);
+                   the W products and sums, M, Cholesky, xi and E_x in FP64 */
 };
 
 enum ace_status {
