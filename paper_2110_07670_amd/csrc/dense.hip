@@ -25,20 +25,24 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
 // 64 x 64 = 4 x 4 MFMA blocks.  K staged through two LDS buffers in slabs of
 // KT: while the MFMAs read one slab, the next one (loaded into registers
 // behind them) is stored into the other buffer, so each slab costs one
-// barrier.
+// barrier.  VEC (even K, 16-byte aligned operands): two consecutive k per
+// load and per LDS store, rows padded to 18 (16-byte aligned, and the MFMA
+// operand reads of 32 lanes still fall on distinct banks); else one k per
+// access, rows padded to 17.
 constexpr int kAbtTile = 128;
 constexpr int kAbtKT = 16;
-constexpr int kAbtPitch = kAbtKT + 1;
 constexpr int kAbtPer = kAbtTile * kAbtKT / 256;  // elements per thread per operand
 
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_abt(const double* __restrict__ A,
                                                   const double* __restrict__ B, int m, int n,
                                                   int64_t K, int64_t kchunk, int tiles_n,
                                                   bool abs_in, double* __restrict__ partial,
                                                   const int* __restrict__ skip) {
   if (skip && *skip != 0) return;
-  __shared__ double sA[2][kAbtTile * kAbtPitch];
-  __shared__ double sB[2][kAbtTile * kAbtPitch];
+  constexpr int kAbtPitch = VEC ? kAbtKT + 2 : kAbtKT + 1;
+  __shared__ __align__(16) double sA[2][kAbtTile * kAbtPitch];
+  __shared__ __align__(16) double sB[2][kAbtTile * kAbtPitch];
   const int tile = blockIdx.x;
   const int split = blockIdx.y;
   const int tm = tile / tiles_n, tn = tile % tiles_n;
@@ -57,27 +61,56 @@ __global__ __launch_bounds__(256) void k_gemm_abt(const double* __restrict__ A,
 
   double ra[kAbtPer], rb[kAbtPer];
   auto fetch = [&](int64_t k0) {
+    if constexpr (VEC) {
+      // element pairs (r, c), (r, c + 1), c even; kend is even
 #pragma unroll
-    for (int q = 0; q < kAbtPer; ++q) {
-      const int e = tid + q * 256;
-      const int r = e / kAbtKT, c = e % kAbtKT;
-      const int64_t k = k0 + c;
-      double va = 0.0, vb = 0.0;
-      if (k < kend) {
-        if (m0 + r < m) va = A[(int64_t)(m0 + r) * K + k];
-        if (n0 + r < n) vb = B[(int64_t)(n0 + r) * K + k];
+      for (int q = 0; q < kAbtPer / 2; ++q) {
+        const int e = tid + q * 256;
+        const int r = e / (kAbtKT / 2), c = 2 * (e % (kAbtKT / 2));
+        const int64_t k = k0 + c;
+        double2 va = {0.0, 0.0}, vb = {0.0, 0.0};
+        if (k < kend) {
+          if (m0 + r < m) va = *reinterpret_cast<const double2*>(A + (int64_t)(m0 + r) * K + k);
+          if (n0 + r < n) vb = *reinterpret_cast<const double2*>(B + (int64_t)(n0 + r) * K + k);
+        }
+        ra[2 * q] = abs_in ? fabs(va.x) : va.x;
+        ra[2 * q + 1] = abs_in ? fabs(va.y) : va.y;
+        rb[2 * q] = abs_in ? fabs(vb.x) : vb.x;
+        rb[2 * q + 1] = abs_in ? fabs(vb.y) : vb.y;
       }
-      ra[q] = abs_in ? fabs(va) : va;
-      rb[q] = abs_in ? fabs(vb) : vb;
+    } else {
+#pragma unroll
+      for (int q = 0; q < kAbtPer; ++q) {
+        const int e = tid + q * 256;
+        const int r = e / kAbtKT, c = e % kAbtKT;
+        const int64_t k = k0 + c;
+        double va = 0.0, vb = 0.0;
+        if (k < kend) {
+          if (m0 + r < m) va = A[(int64_t)(m0 + r) * K + k];
+          if (n0 + r < n) vb = B[(int64_t)(n0 + r) * K + k];
+        }
+        ra[q] = abs_in ? fabs(va) : va;
+        rb[q] = abs_in ? fabs(vb) : vb;
+      }
     }
   };
   auto stage = [&](int buf) {
+    if constexpr (VEC) {
 #pragma unroll
-    for (int q = 0; q < kAbtPer; ++q) {
-      const int e = tid + q * 256;
-      const int r = e / kAbtKT, c = e % kAbtKT;
-      sA[buf][r * kAbtPitch + c] = ra[q];
-      sB[buf][r * kAbtPitch + c] = rb[q];
+      for (int q = 0; q < kAbtPer / 2; ++q) {
+        const int e = tid + q * 256;
+        const int r = e / (kAbtKT / 2), c = 2 * (e % (kAbtKT / 2));
+        *reinterpret_cast<double2*>(&sA[buf][r * kAbtPitch + c]) = double2{ra[2 * q], ra[2 * q + 1]};
+        *reinterpret_cast<double2*>(&sB[buf][r * kAbtPitch + c]) = double2{rb[2 * q], rb[2 * q + 1]};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kAbtPer; ++q) {
+        const int e = tid + q * 256;
+        const int r = e / kAbtKT, c = e % kAbtKT;
+        sA[buf][r * kAbtPitch + c] = ra[q];
+        sB[buf][r * kAbtPitch + c] = rb[q];
+      }
     }
   };
   if (kbeg < kend) {
@@ -160,8 +193,14 @@ hipError_t launch_gemm_abt(const double* A, const double* B, int m, int n, int64
   const int tiles_m = (m + kAbtTile - 1) / kAbtTile, tiles_n = (n + kAbtTile - 1) / kAbtTile;
   int64_t kchunk = (K + nsplit - 1) / nsplit;
   kchunk = ((kchunk + kAbtKT - 1) / kAbtKT) * kAbtKT;
-  hipLaunchKernelGGL(k_gemm_abt, dim3(tiles_m * tiles_n, nsplit), dim3(256), 0, s, A, B, m, n, K,
-                     kchunk, tiles_n, abs_inputs, partial, skip);
+  const bool vec = K % 2 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(B) % 16 == 0;
+  if (vec)
+    hipLaunchKernelGGL(k_gemm_abt<true>, dim3(tiles_m * tiles_n, nsplit), dim3(256), 0, s, A, B,
+                       m, n, K, kchunk, tiles_n, abs_inputs, partial, skip);
+  else
+    hipLaunchKernelGGL(k_gemm_abt<false>, dim3(tiles_m * tiles_n, nsplit), dim3(256), 0, s, A, B,
+                       m, n, K, kchunk, tiles_n, abs_inputs, partial, skip);
   const int64_t count = (int64_t)m * n;
   hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((count + 63) / 64)), dim3(256), 0, s,
                      partial, nsplit, count, scale, C, skip);
