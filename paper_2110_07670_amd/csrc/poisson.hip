@@ -67,6 +67,10 @@ constexpr int fwd_threads() {
 template <int N>
 constexpr int line_chunk() { return (N % 16 == 0) ? 16 : 8; }
 
+// pencils per y-lines workgroup (large grids): 32 where they divide n
+template <int N>
+constexpr int yline_chunk() { return N % 32 == 0 ? 32 : line_chunk<N>(); }
+
 template <int N, int C = line_chunk<N>()>
 constexpr int line_threads() {
   constexpr int N2 = fft_split<N>::N2;
@@ -1110,8 +1114,9 @@ static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs
     hipLaunchKernelGGL((k_rows_fwd<T, N>), dim3((N * N / kRowsPerBlock) * npack),
                        dim3(row_threads<N>()), 0, s, static_cast<const T*>(phi), packs, tw,
                        static_cast<cx<T>*>(S), npack, g.npts);
-    hipLaunchKernelGGL((k_lines<T, N, MODE_FWD>), dim3((N / line_chunk<N>()) * N * npack),
-                       dim3(line_threads<N>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts,
+    hipLaunchKernelGGL((k_lines<T, N, MODE_FWD, yline_chunk<N>()>),
+                       dim3((N / yline_chunk<N>()) * N * npack),
+                       dim3(line_threads<N, yline_chunk<N>()>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts,
                        (int64_t)N, (int64_t)N * N, T(0), T(0), T(0), T(0), (double*)nullptr);
   }
   return hipGetLastError();
@@ -1124,8 +1129,9 @@ static hipError_t inv_yz_t(const GridArgs& g, void* S, int npack, hipStream_t s)
     hipLaunchKernelGGL((k_plane_inv<T, N>), dim3(N * npack), dim3(plane_threads<N>()), 0, s,
                        static_cast<cx<T>*>(S), tw, npack, g.npts);
   } else {
-    hipLaunchKernelGGL((k_lines<T, N, MODE_INV>), dim3((N / line_chunk<N>()) * N * npack),
-                       dim3(line_threads<N>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts,
+    hipLaunchKernelGGL((k_lines<T, N, MODE_INV, yline_chunk<N>()>),
+                       dim3((N / yline_chunk<N>()) * N * npack),
+                       dim3(line_threads<N, yline_chunk<N>()>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts,
                        (int64_t)N, (int64_t)N * N, T(0), T(0), T(0), T(0), (double*)nullptr);
     hipLaunchKernelGGL((k_rows_inv<T, N>), dim3((N * N / kRowsPerBlock) * npack),
                        dim3(row_threads<N>()), 0, s, static_cast<cx<T>*>(S), tw, npack, g.npts);
@@ -1175,8 +1181,9 @@ static hipError_t zinv_t(const GridArgs& g, bool diag, const void* S, const void
 template <typename T, int N>
 static hipError_t inv_y_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
   if constexpr (!plane_ok<T, N>()) {
-    hipLaunchKernelGGL((k_lines<T, N, MODE_INV>), dim3((N / line_chunk<N>()) * N * npack),
-                       dim3(line_threads<N>()), 0, s, static_cast<cx<T>*>(S),
+    hipLaunchKernelGGL((k_lines<T, N, MODE_INV, yline_chunk<N>()>),
+                       dim3((N / yline_chunk<N>()) * N * npack),
+                       dim3(line_threads<N, yline_chunk<N>()>()), 0, s, static_cast<cx<T>*>(S),
                        static_cast<const cx<T>*>(g.tw), npack, g.npts, (int64_t)N, (int64_t)N * N,
                        T(0), T(0), T(0), T(0), (double*)nullptr);
     return hipGetLastError();
