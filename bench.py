@@ -8,13 +8,19 @@ the orbitals, on the 32-water-shaped workload (128 orbitals, 96^3 grid,
 L = 18.6 bohr, all 8256 pairs, FP64).  Inputs are resident in HBM before the
 timed region starts.
 
-Prints one JSON line (rank 0, one GPU).  `roofline` reports the kernel that
-takes the largest share of the step, its algorithmic bytes per launch over its
-average launch time (HIP events on the library's stream, recorded during the
-timed steps), against the 8 TB/s HBM peak; `traffic` is the counter-measured
-HBM bytes per launch of that kernel from the committed rocprofv3 summary, or
-null when the kernel source changed since.  `cpu_baseline` times the FP64
-oracle's pair loop on a bounded sample of the same workload on the host cores.
+Prints one JSON line (rank 0, one GPU).  `value` comes from the timed steps,
+run without any stage events.  The same number of steps is then run again
+with HIP events around every launch on the library's stream: `roofline`
+reports the kernel that takes the largest share of the step, its algorithmic
+bytes per launch over its average launch time from those events, against the
+8 TB/s HBM peak, with the whole pair loop (all transform passes) beside it;
+`hbm_ceilings_GBps` holds what plain streaming kernels of the passes' access
+kinds reach on the same device (read + write in place, read only, write
+only), and each stage is reported against both.  `traffic` is the
+counter-measured HBM bytes per launch of that kernel from the committed
+rocprofv3 summary, or null when the kernel source changed since.
+`cpu_baseline` times the FP64 oracle's pair loop on a bounded sample of the
+same workload on the host cores.
 """
 import argparse
 import hashlib
@@ -132,6 +138,16 @@ def workload_text(spec, precision):
                "FP64" if precision == "fp64" else "FP32 transforms with FP64 W/M/Cholesky/E"))
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(system, spec, n_pairs_sample):
     from oracle import timing
     k = spec.n_orb
@@ -141,9 +157,40 @@ def cpu_baseline(system, spec, n_pairs_sample):
     procs = timing.default_processes()
     rate, secs, used = timing.time_pair_sample(system.phi, spec.cell, spec.alpha, sample, procs)
     return {"value": rate, "unit": "pair-solves/s", "cores": used, "kind": "oracle",
+            "host_cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
             "sample": "%d of %d pairs (every %d-th in i<=j order) of the same %d^3 / %d-orbital "
-                      "workload, oracle FFT pair loop with W updates, %.1f s wall on %d processes"
-                      % (len(sample), len(pairs), step, spec.n, k, secs, used)}
+                      "workload, oracle FFT pair loop with W updates, %.1f s wall on %d processes "
+                      "(one per usable host core, capped at the 16-core share of a one-GPU host; "
+                      "os.cpu_count() = %s)"
+                      % (len(sample), len(pairs), step, spec.n, k, secs, used, os.cpu_count())}
+
+
+def measure_ceilings(torch, dev, gib=2, reps=5):
+    """Achievable HBM rates of plain streaming kernels (include/ace_probe.h) on
+    a buffer far larger than the caches: read + write in place, read only,
+    write only.  GB/s counts the bytes moved (read + written)."""
+    from paper_2110_07670_amd import _lib
+    buf = torch.empty(gib << 30, dtype=torch.uint8, device=dev)
+    blocks = 256 * 16
+    out = {}
+    for kind, factor in (("write", 1), ("read_write", 2), ("read", 1)):
+        _lib.bandwidth_probe(kind, buf, blocks)  # warm
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            _lib.bandwidth_probe(kind, buf, blocks)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        out[kind] = factor * buf.numel() / (ms * 1e-3) / 1e9
+    del buf
+    return out
+
+
+# the probe whose access kind matches each transform pass's traffic
+STAGE_ACCESS = {"yz_fwd": "write", "x_poisson": "read_write", "yz_inv": "read_write",
+                "w_accumulate": "read"}
 
 
 RHO_CUT = {2: 2.5e-2, 3: 1e-2, 5: 2e-3}  # the paper's Table 3 by system size
@@ -425,7 +472,9 @@ def main():
                     help="bulk precision (default: FP64 for configs 1-2 and SCDM, FP32 for "
                          "configs 3-5, as the workloads are specified)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one 1 GiB device copy (for counter calibration runs)")
+                    help="also run one 1 GiB in-place streaming pass (counter calibration runs)")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the streaming-probe measurement of the achievable HBM rates")
     ap.add_argument("--screen", choices=["mlp", "overlap"], default=None,
                     help="measure a screened build against the all-pairs build instead")
     args = ap.parse_args()
@@ -473,30 +522,38 @@ def main():
         _lib.apply_into(plan, xi, phi, out, ws_apply)
 
     if args.copy_calibration:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1.0)
+        # a known-size in-place streaming pass (1 GiB read + 1 GiB written)
+        # for scaling the FETCH_SIZE / WRITE_SIZE counters of the same run
+        cal = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        _lib.bandwidth_probe("read_write", cal, 256 * 16)
         torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        del cal
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    plan.set_profiling(True)
-    torch.cuda.synchronize()
+    # the timed steps run without stage events (value); the same number of
+    # steps is then run again with HIP events around every launch on the
+    # library's stream for the per-stage and per-kernel times
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = plan.profile_read()
-    plan.set_profiling(False)
     assert int(info.item()) == 0, "Cholesky of -M failed"
     elapsed = t1 - t0
     value = spec.n_pairs * args.steps / elapsed
     ms_per_step = 1000.0 * elapsed / args.steps
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    prof = plan.profile_read()
+    plan.set_profiling(False)
+    ceilings = None if args.no_ceilings else measure_ceilings(torch, dev)
 
     bulk = 8 if args.precision == "fp64" else 4
     tiles = tile_plan(spec.n_orb, plan.tiling[0], spec.n, bulk, plan.four_pass)
@@ -510,7 +567,13 @@ def main():
         if name in stages:
             ab = algorithmic_bytes(name, tiles, npts, bulk, plane_fits(spec.n, bulk))
             launch_ms = stages[name]["ms_per_step"] / stages[name]["launches_per_step"]
-            stages[name]["alg_GBps"] = ab / (stages[name]["ms_per_step"] * 1e-3) / 1e9
+            gbps = ab / (stages[name]["ms_per_step"] * 1e-3) / 1e9
+            stages[name]["alg_GBps"] = gbps
+            stages[name]["frac_of_peak"] = gbps / HBM_PEAK_GBPS
+            if ceilings:
+                acc = STAGE_ACCESS[name]
+                stages[name]["ceiling_kind"] = acc
+                stages[name]["frac_of_ceiling"] = gbps / ceilings[acc]
             stages[name]["alg_bytes_per_launch"] = ab / stages[name]["launches_per_step"]
             stages[name]["avg_launch_ms"] = launch_ms
     # FP64 MFMA products: M = dV Phi^T W and xi = W L^-T (2 n^2 N flops each),
@@ -526,9 +589,17 @@ def main():
     d = stages[dom]
     achieved = d["alg_bytes_per_launch"] / (d["avg_launch_ms"] * 1e-3) / 1e9
     traffic = read_traffic(dom) if (args.config, args.precision) == (2, "fp64") else None
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic}
     pair_loop_ms = sum(stages[s]["ms_per_step"] for s in mem_stages if s in stages)
+    # the survey's algorithmic bytes: 32 B (FP64) or 16 B (FP32) per point per pair
+    loop_bytes = spec.n_pairs * 4.0 * bulk * npts
+    loop_gbps = loop_bytes / (pair_loop_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                "pair_loop": {"ms": pair_loop_ms, "alg_bytes": loop_bytes,
+                              "achieved": loop_gbps, "frac": loop_gbps / HBM_PEAK_GBPS}}
+    if ceilings:
+        roofline["frac_of_ceiling"] = achieved / ceilings[STAGE_ACCESS[dom]]
+        roofline["pair_loop"]["frac_of_copy_ceiling"] = loop_gbps / ceilings["read_write"]
 
     result = {
         "metric": "orbital-pair Poisson solves/s in ACE build (128 orb, 96^3) + % HBM roofline",
@@ -548,7 +619,8 @@ def main():
                    "tiling": list(plan.tiling)},
         "roofline": roofline,
         "pair_loop_ms": pair_loop_ms,
-        "pair_loop_alg_GBps_32B": spec.n_pairs * 4.0 * bulk * npts / (pair_loop_ms * 1e-3) / 1e9,
+        "profiled_ms_per_step": 1000.0 * (tp1 - tp0) / args.steps,
+        "hbm_ceilings_GBps": ceilings,
         "stages": stages,
         "ex": float(ex.item()),
     }

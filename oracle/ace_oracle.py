@@ -136,13 +136,25 @@ def apply_vx(phi: np.ndarray, cell: np.ndarray, alpha: float,
 
 
 def apply_vx_rows(phi: np.ndarray, cell: np.ndarray, alpha: float, rows,
+                  pair_mask: Optional[np.ndarray] = None, cols=None,
                   workers: int = 1) -> np.ndarray:
-    """W_i for selected i only (all j): -alpha sum_j v_ij phi_j.  For sampled checks."""
+    """Selected rows of Eq. (2): W_i = -alpha sum_j v_ij phi_j for i in ``rows``.
+
+    The sum runs over j in ``cols`` (default: every orbital, in increasing
+    order), skipping pairs whose upper-triangle ``pair_mask`` entry
+    (min(i, j), max(i, j)) is zero.  Summing the results of disjoint ``cols``
+    gives the full row, so a row can be split over processes.  For a row i
+    the unordered-pair loop of apply_vx adds the same terms in the same
+    order (j = 0, 1, ...), so the two agree to rounding.
+    """
     phi = np.asarray(phi, dtype=np.float64)
     K = coulomb_kernel(phi.shape[1:], cell)
+    js = range(phi.shape[0]) if cols is None else cols
     out = np.zeros((len(rows),) + phi.shape[1:])
     for a, i in enumerate(rows):
-        for j in range(phi.shape[0]):
+        for j in js:
+            if pair_mask is not None and not pair_mask[min(i, j), max(i, j)]:
+                continue
             v = pair_potential(phi[i] * phi[j], K, workers)
             out[a] -= alpha * v * phi[j]
     return out

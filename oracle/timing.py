@@ -57,30 +57,10 @@ def time_pair_sample(phi: np.ndarray, cell: np.ndarray, alpha: float,
 
 
 def default_processes() -> int:
-    n = os.cpu_count() or 1
+    """Host processes for the timed sample: every core the process may use,
+    capped at 16 (the CPU share a one-GPU host gives a job)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
     return max(1, min(n, 16))
-
-
-def _row_chunk(args):
-    i, js = args
-    w = np.zeros_like(_PHI[i])
-    for j in js:
-        w -= _ALPHA * O.pair_potential(_PHI[i] * _PHI[j], _K, workers=1) * _PHI[j]
-    return i, w
-
-
-def apply_vx_rows_parallel(phi: np.ndarray, cell: np.ndarray, alpha: float, rows,
-                           processes: int):
-    """W_i = -alpha sum_j v_ij phi_j for the given rows, the j sum split over processes
-    and added back in a fixed order."""
-    K = O.coulomb_kernel(phi.shape[1:], cell)
-    k = phi.shape[0]
-    processes = max(1, processes)
-    jobs = [(i, list(range(c, k, processes))) for i in rows for c in range(processes)]
-    ctx = mp.get_context("fork")
-    with ctx.Pool(processes, initializer=_init, initargs=(phi, K, alpha)) as pool:
-        parts = pool.map(_row_chunk, jobs)
-    out = {i: np.zeros_like(phi[0]) for i in rows}
-    for i, w in parts:
-        out[i] += w
-    return out

@@ -28,6 +28,8 @@ EXPORTS = ["ace_plan_create", "ace_plan_destroy", "ace_workspace_bytes",
            "ace_mlp_weight_count", "ace_batch_create", "ace_batch_destroy",
            "ace_batch_workspace_bytes", "ace_batch_build", "scdm_workspace_bytes",
            "scdm_preselect", "scdm_localize"]
+PROBE_EXPORTS = ["ace_bandwidth_probe"]
+PROBE_KINDS = {"read_write": 0, "read": 1, "write": 2}
 ACE_BATCH_MAX = 1024
 ACE_BATCH_EAGER = 1
 
@@ -110,6 +112,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.scdm_preselect.restype = i
     lib.scdm_localize.argtypes = [vp, vp, vp, sz, vp, vp, i, vp, vp, vp]
     lib.scdm_localize.restype = i
+    lib.ace_bandwidth_probe.argtypes = [i, vp, vp, sz, i]
+    lib.ace_bandwidth_probe.restype = i
     _LIB = lib
     return lib
 
@@ -145,6 +149,45 @@ def _mask_buffer(mask, n_orb: int):
     return m, m.ctypes.data
 
 
+def _tensor(t, name: str, shape=None, dtype: str = "float64", device=None, min_bytes: int = 0,
+            cuda: bool = True):
+    """Check that t is a contiguous device tensor of the given dtype and shape
+    (and on `device`) before its address reaches a kernel: the C-ABI sees
+    only pointers, so a wrong size or a host tensor would be read or written
+    out of bounds on the GPU.  Raises ValueError."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor, got %s" % (name, type(t).__name__))
+    if dtype is not None and t.dtype != getattr(torch, dtype):
+        raise ValueError("%s must be %s (is %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s (has %s)" % (name, tuple(shape), tuple(t.shape)))
+    if t.numel() * t.element_size() < min_bytes:
+        raise ValueError("%s holds %d bytes, the call needs %d"
+                         % (name, t.numel() * t.element_size(), min_bytes))
+    if cuda:
+        _on_device(device, (name, t))
+    return t
+
+
+def _on_device(device, *named):
+    """Every (name, tensor) is a device tensor, on `device` (default: the
+    first one's) and on the current device."""
+    import torch
+    for name, t in named:
+        if not t.is_cuda:
+            raise ValueError("%s must be a device tensor (is on %s)" % (name, t.device))
+        if device is None:
+            device = t.device
+        if t.device != device:
+            raise ValueError("%s is on %s, expected %s" % (name, t.device, device))
+        if t.device.index != torch.cuda.current_device():
+            raise ValueError("%s is on %s but the current device is cuda:%d"
+                             % (name, t.device, torch.cuda.current_device()))
+
+
 class Plan:
     """A host-only ACE plan (grid, cell, orbital count, precision, alpha)."""
 
@@ -165,6 +208,7 @@ class Plan:
         _check(lib.ace_plan_create(ctypes.byref(h), ctypes.byref(d)), "ace_plan_create")
         self._h = h
         self.n, self.cell, self.n_orb, self.alpha = g[0], cl, int(n_orb), float(alpha)
+        self.grid = tuple(int(v) for v in g)
         self.precision = d.precision
         self.npts = g[0] * g[1] * g[2]
         self.tiling = (16, 0, 0)
@@ -184,6 +228,14 @@ class Plan:
 
     def apply_workspace_bytes(self, n_vec: int) -> int:
         return int(load().ace_apply_workspace_bytes(self._h, int(n_vec)))
+
+    def orbital_shape(self, count: Optional[int] = None):
+        return (self.n_orb if count is None else int(count),) + self.grid
+
+    def check_orbitals(self, t, name: str = "phi", count: Optional[int] = None, device=None,
+                       cuda: bool = True):
+        """Validate an orbital-major float64 (device) tensor for this plan."""
+        return _tensor(t, name, self.orbital_shape(count), device=device, cuda=cuda)
 
     def set_tiling(self, block: int, chunk: int = 0, pencils: int = 0):
         _check(load().ace_plan_set_tiling(self._h, int(block), int(chunk), int(pencils)),
@@ -213,6 +265,15 @@ def workspace(nbytes: int, device="cuda"):
 
 def build_into(plan: Plan, phi, W, M, xi, ex, info, ws, pair_mask=None, stream=None):
     """ace_build on caller-provided torch tensors (no allocation)."""
+    plan.check_orbitals(phi, cuda=False)
+    plan.check_orbitals(W, "W", cuda=False)
+    plan.check_orbitals(xi, "xi", cuda=False)
+    _tensor(M, "M", (plan.n_orb, plan.n_orb), cuda=False)
+    _tensor(ex, "ex", None, min_bytes=8, cuda=False)
+    _tensor(info, "info", None, "int32", min_bytes=4, cuda=False)
+    _tensor(ws, "ws", None, None, min_bytes=plan.workspace_bytes(), cuda=False)
+    _on_device(None, ("phi", phi), ("W", W), ("xi", xi), ("M", M), ("ex", ex), ("info", info),
+               ("ws", ws))
     m, mptr = _mask_buffer(pair_mask, plan.n_orb)
     rc = load().ace_build(plan.handle, _stream(stream), _ptr(ws), ws.numel() * ws.element_size(),
                           _ptr(phi), mptr or None, _ptr(W), _ptr(M), _ptr(xi), _ptr(ex), _ptr(info))
@@ -222,6 +283,7 @@ def build_into(plan: Plan, phi, W, M, xi, ex, info, ws, pair_mask=None, stream=N
 def ace_build(plan: Plan, phi, pair_mask=None, ws=None, stream=None):
     """W, M, xi, ex, info as torch tensors on phi's device."""
     import torch
+    plan.check_orbitals(phi)
     dev = phi.device
     k = plan.n_orb
     W = torch.empty_like(phi)
@@ -236,7 +298,16 @@ def ace_build(plan: Plan, phi, pair_mask=None, ws=None, stream=None):
 
 
 def apply_into(plan: Plan, xi, psi, out, ws, stream=None):
+    plan.check_orbitals(xi, "xi", cuda=False)
+    if not hasattr(psi, "shape") or psi.dim() != 4:
+        raise ValueError("psi must be a (n_vec, n1, n2, n3) tensor")
     n_vec = int(psi.shape[0])
+    if n_vec < 1:
+        raise ValueError("psi holds no vectors")
+    plan.check_orbitals(psi, "psi", count=n_vec, cuda=False)
+    plan.check_orbitals(out, "out", count=n_vec, cuda=False)
+    _tensor(ws, "ws", None, None, min_bytes=plan.apply_workspace_bytes(n_vec), cuda=False)
+    _on_device(None, ("xi", xi), ("psi", psi), ("out", out), ("ws", ws))
     rc = load().ace_apply(plan.handle, _stream(stream), _ptr(ws), ws.numel() * ws.element_size(),
                           _ptr(xi), _ptr(psi), n_vec, _ptr(out))
     _check(rc, "ace_apply")
@@ -244,6 +315,11 @@ def apply_into(plan: Plan, xi, psi, out, ws, stream=None):
 
 def ace_apply(plan: Plan, xi, psi, ws=None, stream=None):
     import torch
+    plan.check_orbitals(xi, "xi", cuda=False)
+    if not hasattr(psi, "shape") or psi.dim() != 4:
+        raise ValueError("psi must be a (n_vec, n1, n2, n3) tensor")
+    plan.check_orbitals(psi, "psi", count=int(psi.shape[0]), cuda=False)
+    _on_device(None, ("xi", xi), ("psi", psi))
     out = torch.empty_like(psi)
     if ws is None:
         ws = workspace(plan.apply_workspace_bytes(int(psi.shape[0])), psi.device)
@@ -254,11 +330,13 @@ def ace_apply(plan: Plan, xi, psi, ws=None, stream=None):
 def exx_energy(plan: Plan, phi, pair_mask=None, pair_energies: bool = False, ws=None, stream=None):
     """(ex tensor[1], pair_e tensor[n_orb, n_orb] or None)."""
     import torch
+    plan.check_orbitals(phi)
     dev = phi.device
     ex = torch.zeros((1,), dtype=torch.float64, device=dev)
     pe = torch.zeros((plan.n_orb, plan.n_orb), dtype=torch.float64, device=dev) if pair_energies else None
     if ws is None:
         ws = workspace(plan.workspace_bytes(), dev)
+    _tensor(ws, "ws", None, None, device=dev, min_bytes=plan.workspace_bytes())
     m, mptr = _mask_buffer(pair_mask, plan.n_orb)
     rc = load().exx_energy(plan.handle, _stream(stream), _ptr(ws), ws.numel() * ws.element_size(),
                            _ptr(phi), mptr or None, _ptr(ex), _ptr(pe))
@@ -271,9 +349,11 @@ def exx_energy(plan: Plan, phi, pair_mask=None, pair_energies: bool = False, ws=
 def overlap_integrals(plan: Plan, phi, ws=None, stream=None):
     """S[i, j] = dV sum_r |phi_i| |phi_j| (device float64 [n_orb, n_orb])."""
     import torch
+    plan.check_orbitals(phi)
     S = torch.empty((plan.n_orb, plan.n_orb), dtype=torch.float64, device=phi.device)
     if ws is None:
         ws = workspace(plan.workspace_bytes(), phi.device)
+    _tensor(ws, "ws", None, None, device=phi.device, min_bytes=plan.workspace_bytes())
     rc = load().ace_overlap_integrals(plan.handle, _stream(stream), _ptr(ws),
                                       ws.numel() * ws.element_size(), _ptr(phi), _ptr(S))
     _check(rc, "ace_overlap_integrals")
@@ -284,6 +364,7 @@ def wannier(plan: Plan, phi, stream=None):
     """(z [n_orb, 6], feat [n_orb, 4]) device float64: Berry-phase moments and
     (centre xyz, spread) of each orbital density."""
     import torch
+    plan.check_orbitals(phi)
     z = torch.empty((plan.n_orb, 6), dtype=torch.float64, device=phi.device)
     feat = torch.empty((plan.n_orb, 4), dtype=torch.float64, device=phi.device)
     rc = load().ace_wannier(plan.handle, _stream(stream), _ptr(phi), _ptr(z), _ptr(feat))
@@ -299,10 +380,10 @@ def mlp_screen(plan: Plan, feat, weights, stream=None):
     """pred [n_orb, n_orb] device float32: predicted log10 |e_ij| for i <= j
     (entries below the diagonal are NaN)."""
     import torch
+    _tensor(feat, "feat", (plan.n_orb, 4))
     w = weights if hasattr(weights, "data_ptr") else torch.from_numpy(
         np.ascontiguousarray(weights, dtype=np.float32)).to(feat.device)
-    if w.numel() != mlp_weight_count():
-        raise ValueError("expected %d MLP weights" % mlp_weight_count())
+    _tensor(w, "weights", (mlp_weight_count(),), "float32", device=feat.device)
     pred = torch.full((plan.n_orb, plan.n_orb), float("nan"), dtype=torch.float32,
                       device=feat.device)
     rc = load().ace_mlp_screen(plan.handle, _stream(stream), _ptr(feat), _ptr(w), _ptr(pred))
@@ -363,6 +444,20 @@ class Batch:
     def build_into(self, phis, out, ws, eager: bool = False, stream=None):
         if len(phis) != len(self.plans):
             raise ValueError("expected %d orbital sets" % len(self.plans))
+        for key in ("W", "M", "xi"):
+            if len(out[key]) != len(self.plans):
+                raise ValueError("expected %d %s tensors" % (len(self.plans), key))
+        named = []
+        for k, p in enumerate(self.plans):
+            for key, t in (("phis", phis[k]), ("W", out["W"][k]), ("xi", out["xi"][k])):
+                p.check_orbitals(t, "%s[%d]" % (key, k), cuda=False)
+                named.append(("%s[%d]" % (key, k), t))
+            _tensor(out["M"][k], "M[%d]" % k, (p.n_orb, p.n_orb), cuda=False)
+            named.append(("M[%d]" % k, out["M"][k]))
+        _tensor(out["ex"], "ex", (len(self.plans),), cuda=False)
+        _tensor(out["info"], "info", (len(self.plans),), "int32", cuda=False)
+        _tensor(ws, "ws", None, None, min_bytes=self.workspace_bytes(), cuda=False)
+        _on_device(None, *named, ("ex", out["ex"]), ("info", out["info"]), ("ws", ws))
         rc = load().ace_batch_build(self._h, _stream(stream), _ptr(ws),
                                     ws.numel() * ws.element_size(), _ptr_array(phis),
                                     _ptr_array(out["W"]), _ptr_array(out["M"]),
@@ -383,8 +478,11 @@ class Batch:
 def scdm_preselect(plan: Plan, phi, ws=None, stream=None):
     """Kept grid points of the s' rule (device int32 tensor, increasing)."""
     import torch
+    plan.check_orbitals(phi)
     if ws is None:
         ws = workspace(int(load().scdm_workspace_bytes(plan.handle, 0)), phi.device)
+    _tensor(ws, "ws", None, None, device=phi.device,
+            min_bytes=int(load().scdm_workspace_bytes(plan.handle, 0)))
     points = torch.empty((plan.npts,), dtype=torch.int32, device=phi.device)
     count = torch.zeros((1,), dtype=torch.int32, device=phi.device)
     rc = load().scdm_preselect(plan.handle, _stream(stream), _ptr(ws),
@@ -399,9 +497,14 @@ def scdm_localize(plan: Plan, phi, points=None, ws=None, stream=None):
     """(pivots [n_orb] int32, phi_loc like phi, info [1] int32) on the device;
     points None: every grid point."""
     import torch
+    plan.check_orbitals(phi)
     m = plan.npts if points is None else int(points.numel())
+    if points is not None:
+        _tensor(points, "points", (m,), "int32", device=phi.device)
     if ws is None:
         ws = workspace(int(load().scdm_workspace_bytes(plan.handle, m)), phi.device)
+    _tensor(ws, "ws", None, None, device=phi.device,
+            min_bytes=int(load().scdm_workspace_bytes(plan.handle, m)))
     pivots = torch.empty((plan.n_orb,), dtype=torch.int32, device=phi.device)
     loc = torch.empty_like(phi)
     info = torch.zeros((1,), dtype=torch.int32, device=phi.device)
@@ -417,3 +520,15 @@ def scdm(plan: Plan, phi, preselect: bool = True, stream=None):
     pts = scdm_preselect(plan, phi, stream=stream) if preselect else None
     pivots, loc, info = scdm_localize(plan, phi, pts, stream=stream)
     return {"points": pts, "pivots": pivots, "phi_loc": loc, "info": info}
+
+
+# ------------------------------------------------------------------ bandwidth probes
+
+def bandwidth_probe(kind: str, buf, blocks: int, stream=None):
+    """One streaming launch over the device tensor `buf` (include/ace_probe.h):
+    kind 'read_write' (in place), 'read' or 'write'."""
+    _tensor(buf, "buf", None, None, min_bytes=16)
+    rc = load().ace_bandwidth_probe(PROBE_KINDS[kind], _stream(stream), _ptr(buf),
+                                    buf.numel() * buf.element_size(), int(blocks))
+    if rc != 0:
+        raise RuntimeError("ace_bandwidth_probe(%s) returned %d" % (kind, rc))

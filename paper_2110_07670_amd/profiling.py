@@ -3,8 +3,9 @@
 Reads the rocpd SQLite databases of three runs of the same command:
 a kernel trace with --stats, a --pmc FETCH_SIZE run and a --pmc WRITE_SIZE
 run.  HBM bytes per dispatch are the counters (KiB) scaled by what the same
-counters read for a plain 1 GiB device copy in the same process
-(bench.py --copy-calibration), whose true traffic is 1 GiB read + 1 GiB written.
+counters read for a known streaming pass in the same process
+(bench.py --copy-calibration: one in-place read + write launch over 1 GiB,
+k_probe_rw, whose true traffic is 1 GiB read + 1 GiB written).
 
 Usage: python -m paper_2110_07670_amd.profiling TRACE_DB FETCH_DB WRITE_DB OUT.md "COMMAND"
        python -m paper_2110_07670_amd.profiling --trace-only TRACE_DB OUT.md "TITLE" "COMMAND"
@@ -65,14 +66,19 @@ def counters(db_path: str, counter: str):
     return [(d, _short(k), float(v), float(dur)) for d, k, v, dur in rows]
 
 
+CALIBRATION_KERNEL = "k_probe_rw"
+
+
 def calibration(fetch, write):
-    """(fetch factor, write factor): true KiB / counter KiB for the 1 GiB copy."""
+    """(fetch factor, write factor): true KiB / counter KiB for the 1 GiB
+    in-place streaming pass."""
     true_kib = float(1 << 20)
-    cf = [v for _, k, v, _ in fetch if "copyBuffer" in k]
-    cw = [v for _, k, v, _ in write if "copyBuffer" in k]
-    f = true_kib / max(cf) if cf else 1.0
-    w = true_kib / max(cw) if cw else 1.0
-    return f, w
+    cf = [v for _, k, v, _ in fetch if CALIBRATION_KERNEL in k]
+    cw = [v for _, k, v, _ in write if CALIBRATION_KERNEL in k]
+    if not cf or not cw:
+        raise SystemExit("no %s dispatch in the counter runs (bench.py --copy-calibration)"
+                         % CALIBRATION_KERNEL)
+    return true_kib / max(cf), true_kib / max(cw)
 
 
 def summarize(trace_db, fetch_db, write_db, out_md, command):
@@ -88,8 +94,9 @@ def summarize(trace_db, fetch_db, write_db, out_md, command):
     stage_bytes = collections.defaultdict(list)
     lines = ["# rocprofv3 summary: ACE build, water32_n96 (128 orbitals, 96^3, FP64)", "",
              "Commands (run from the repository root on one MI355X):", "", "```", command, "```", "",
-             "Copy calibration (1 GiB device copy in the same process): FETCH_SIZE x %.3f, "
-             "WRITE_SIZE x %.3f give true bytes." % (ff, fw), "",
+             "Counter calibration (one in-place read + write launch over 1 GiB in the same "
+             "process, %s): FETCH_SIZE x %.3f, WRITE_SIZE x %.3f give true bytes."
+             % (CALIBRATION_KERNEL, ff, fw), "",
              "| kernel | calls | avg us | total ms | HBM read MB/launch | HBM write MB/launch |",
              "|---|---|---|---|---|---|"]
     for k, (calls, tot) in stats.items():

@@ -13,8 +13,8 @@ from paper_2110_07670_amd import _lib
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    text = open(os.path.join(ROOT, "include", "ace.h")).read()
+def _declared(header="ace.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b((?:ace|exx|scdm)_[a-z_]+)\s*\(", text)))
 
@@ -26,6 +26,21 @@ def test_library_exports_every_declared_call():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(_lib.EXPORTS)
+    probes = _declared("ace_probe.h")
+    assert probes == sorted(_lib.PROBE_EXPORTS)
+    for n in probes:
+        assert hasattr(lib, n), n
+
+
+def test_bandwidth_probe_rejects_bad_arguments():
+    lib = _lib.load()
+    buf = ctypes.create_string_buffer(64)
+    addr = (ctypes.addressof(buf) + 15) & ~15
+    assert lib.ace_bandwidth_probe(0, None, None, 64, 1) == 1
+    assert lib.ace_bandwidth_probe(3, None, addr, 32, 1) == 1
+    assert lib.ace_bandwidth_probe(0, None, addr + 8, 32, 1) == 1
+    assert lib.ace_bandwidth_probe(1, None, addr, 8, 1) == 1
+    assert lib.ace_bandwidth_probe(2, None, addr, 32, 0) == 1
 
 
 def _desc(n=32, L=10.0, k=8, prec=0, alpha=0.25, grid=None):
@@ -241,3 +256,71 @@ def test_scdm_validation_before_device():
     if torch.cuda.device_count() == 0:
         assert f(h, None, ws, loc, phi, pts, 100, piv, out, info) == _lib.ACE_ERR_NODEV
     lib.ace_plan_destroy(h)
+
+
+# ----------------------------------------------------------------------- binding checks
+# The C-ABI sees only pointers, so the binding must refuse tensors of the
+# wrong kind before any address reaches a kernel.
+
+@pytest.fixture(scope="module")
+def plan16():
+    return _lib.Plan(16, (8.0, 8.0, 8.0), 4, "fp64", 0.25)
+
+
+def _cpu(shape, dtype="float64"):
+    import torch
+    return torch.zeros(shape, dtype=getattr(torch, dtype))
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (lambda: _cpu((4, 16, 16, 16), "float32"), "float64"),
+    (lambda: _cpu((4, 16, 16, 32))[..., ::2], "contiguous"),
+    (lambda: _cpu((3, 16, 16, 16)), "shape"),
+    (lambda: _cpu((4, 16, 16, 8)), "shape"),
+    (lambda: _cpu((4, 16, 16, 16)), "device tensor"),
+    (lambda: np.zeros((4, 16, 16, 16)), "torch tensor"),
+])
+def test_binding_rejects_bad_orbitals(plan16, bad, msg):
+    phi = bad()
+    for call in (lambda: _lib.ace_build(plan16, phi),
+                 lambda: _lib.exx_energy(plan16, phi),
+                 lambda: _lib.overlap_integrals(plan16, phi),
+                 lambda: _lib.wannier(plan16, phi),
+                 lambda: _lib.scdm_preselect(plan16, phi)):
+        with pytest.raises(ValueError, match=msg):
+            call()
+
+
+def test_binding_rejects_bad_apply_and_outputs(plan16):
+    xi = _cpu((4, 16, 16, 16))
+    with pytest.raises(ValueError, match="float64"):
+        _lib.ace_apply(plan16, xi.float(), xi)
+    with pytest.raises(ValueError, match="shape"):
+        _lib.ace_apply(plan16, xi, _cpu((2, 16, 16, 8)))
+    with pytest.raises(ValueError, match="device tensor"):
+        _lib.ace_apply(plan16, xi, _cpu((2, 16, 16, 16)))
+    M = _cpu((4, 4))
+    ex, info = _cpu((1,)), _cpu((1,), "int32")
+    ws = _cpu((plan16.workspace_bytes(),), "uint8")
+    with pytest.raises(ValueError, match="shape"):
+        _lib.build_into(plan16, xi, xi, _cpu((4, 5)), xi, ex, info, ws)
+    with pytest.raises(ValueError, match="int32"):
+        _lib.build_into(plan16, xi, xi, M, xi, ex, _cpu((1,)), ws)
+    with pytest.raises(ValueError, match="bytes"):
+        _lib.build_into(plan16, xi, xi, M, xi, ex, info, ws[:16])
+    with pytest.raises(ValueError, match="device tensor"):
+        _lib.build_into(plan16, xi, xi, M, xi, ex, info, ws)
+
+
+def test_binding_rejects_bad_batch_inputs(plan16):
+    b = _lib.Batch([plan16])
+    phi = _cpu((4, 16, 16, 16))
+    out = {"W": [phi], "M": [_cpu((4, 4))], "xi": [phi], "ex": _cpu((1,)),
+           "info": _cpu((1,), "int32")}
+    ws = _cpu((b.workspace_bytes(),), "uint8")
+    with pytest.raises(ValueError, match="expected 1 orbital sets"):
+        b.build_into([phi, phi], out, ws)
+    with pytest.raises(ValueError, match="shape"):
+        b.build_into([_cpu((4, 16, 16, 8))], out, ws)
+    with pytest.raises(ValueError, match="device tensor"):
+        b.build_into([phi], out, ws)

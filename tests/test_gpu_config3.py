@@ -1,6 +1,8 @@
 """Config 3 (64 waters, 256 orbitals, 128^3): FP64 parity and the FP32-bulk
-errors, both against the FP64 oracle (committed reference values from
-tests/golden/make_reference.py, plus one oracle W row computed here)."""
+errors, both against the FP64 oracle: committed references from
+tests/golden/make_reference.py (E_x from all 32,896 pair energies, the full
+M from every oracle W row) and one oracle W row of Eq. (2) computed in a
+separate process (tests/oracle_job.py)."""
 import json
 import os
 import sys
@@ -9,12 +11,12 @@ import numpy as np
 import pytest
 
 from oracle import ace_oracle as O
-from oracle import timing
 from paper_2110_07670_amd import synth
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 REF = os.path.join(HERE, "golden", "reference_config3.json")
+M_FULL = os.path.join(HERE, "golden", "M_full_config3.npz")
 
 
 def _say(*a):
@@ -22,17 +24,16 @@ def _say(*a):
 
 
 @pytest.fixture(scope="module")
-def setup():
+def setup(oracle_job):
     ref = json.load(open(REF))
     spec = synth.config(3)
     s = synth.build_system(spec)
     sys.path.insert(0, os.path.join(HERE, "golden"))
     from make_reference import fingerprint_matches
     assert fingerprint_matches(s.phi, ref["phi_fingerprint"]), "generator drift: regenerate"
-    row = 77
-    # the oracle's process pool forks before this process initialises the GPU
-    w_ref = timing.apply_vx_rows_parallel(s.phi, spec.cell, spec.alpha, [row],
-                                          timing.default_processes())[row]
+    rows, w = oracle_job.result("config3_row77")
+    row, w_ref = rows[0], np.array(w[0])
+    ref["M_full"] = np.load(M_FULL)["M"]
     import torch
     from paper_2110_07670_amd import _lib
     assert torch.cuda.is_available()
@@ -53,6 +54,8 @@ def _run(setup, precision):
     res["ex_err"] = abs(res["ex"] - ref["ex"])
     res["ex_err_per_atom"] = res["ex_err"] / spec.n_atoms
     res["M_rows_err"] = max(O.rel_err(M[int(i)], np.array(v)) for i, v in ref["M_rows"].items())
+    res["M_err"] = O.rel_err(M, ref["M_full"])
+    res["M_elem_err"] = float(np.abs(M - ref["M_full"]).max() / np.abs(ref["M_full"]).max())
     res["W_row_err"] = O.rel_err(W[row], w_ref)
     res["ace_row_err"] = O.rel_err(back.cpu().numpy()[0], w_ref)
     return res
@@ -65,6 +68,7 @@ def test_config3_fp64_parity(setup):
     assert r["info"] == 0
     assert r["ex_err"] < 1e-10 * abs(setup[2]["ex"])
     assert r["M_rows_err"] < 1e-10
+    assert r["M_err"] < 1e-10 and r["M_elem_err"] < 1e-10
     assert r["W_row_err"] < 1e-10
     assert r["ace_row_err"] < 1e-10
 
@@ -77,5 +81,6 @@ def test_config3_fp32_bulk_errors(setup):
     assert r["info"] == 0
     assert r["ex_err_per_atom"] < 1e-6
     assert r["M_rows_err"] < 1e-5
+    assert r["M_err"] < 1e-5
     assert r["W_row_err"] < 1e-5
     assert r["ace_row_err"] < 1e-5

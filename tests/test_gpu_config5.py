@@ -18,7 +18,6 @@ import numpy as np
 import pytest
 
 from oracle import ace_oracle as O
-from oracle import timing
 from paper_2110_07670_amd import screening, synth
 
 pytestmark = pytest.mark.gpu
@@ -36,7 +35,7 @@ def _say(*a):
 
 
 @pytest.fixture(scope="module")
-def setup():
+def setup(oracle_job):
     if not os.path.exists(REF):
         pytest.skip("no committed oracle reference for config 5")
     ref = json.load(open(REF))
@@ -46,9 +45,9 @@ def setup():
     sys.path.insert(0, os.path.join(HERE, "golden"))
     from make_reference import fingerprint_matches
     assert fingerprint_matches(s.phi, ref["phi_fingerprint"]), "generator drift: regenerate"
-    # the oracle's process pool forks before this process initialises the GPU
-    w_ref = timing.apply_vx_rows_parallel(s.phi, spec.cell, spec.alpha, [ROW],
-                                          timing.default_processes())[ROW]
+    rows, w = oracle_job.result("config5_row255")
+    assert rows == [ROW]
+    w_ref = np.array(w[0])
     import torch
     from paper_2110_07670_amd import _lib
     assert torch.cuda.is_available()
@@ -56,16 +55,6 @@ def setup():
     plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, "fp32", spec.alpha)
     return dict(spec=spec, s=s, ref=ref, e_pairs=e_pairs, w_ref=w_ref, lib=_lib, phi=phi,
                 plan=plan)
-
-
-def _masked_row_oracle(phi, cell, alpha, i, mask):
-    """W_i = -alpha sum over kept j of v_ij phi_j (Eq. (2) restricted to the kept pairs)."""
-    K = O.coulomb_kernel(phi.shape[1:], cell)
-    w = np.zeros_like(phi[i])
-    for j in range(phi.shape[0]):
-        if mask[min(i, j), max(i, j)]:
-            w -= alpha * O.pair_potential(phi[i] * phi[j], K) * phi[j]
-    return w
 
 
 def _build(st, mask=None):
@@ -106,7 +95,9 @@ def _check_screened(st, mask, label):
     err_total = abs(r["ex"] - ref["ex"]) / spec.n_atoms
     err_fp32 = abs(r["ex"] - ex_masked_oracle) / spec.n_atoms
     skipped = abs(ref["ex"] - ex_masked_oracle) / spec.n_atoms
-    w_mask = _masked_row_oracle(st["s"].phi, spec.cell, spec.alpha, ROW, mask)
+    threads = min(16, os.cpu_count() or 1)
+    w_mask = O.apply_vx_rows(st["s"].phi, spec.cell, spec.alpha, [ROW], pair_mask=mask,
+                             workers=threads)[0]
     w_err = O.rel_err(r["W_row"], w_mask)
     print("config5 %s screen: %d of %d pairs kept; E_x %.12f; error vs oracle all pairs "
           "%.2e Ha/atom (skipped pairs %.2e, FP32 path %.2e); masked W row %.2e"

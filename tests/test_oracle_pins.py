@@ -312,6 +312,68 @@ def test_pair_mask_skips_pairs_and_shards_sum(small):
     assert O.rel_err(Ws, out["W"]) < 1e-13
 
 
+@pytest.fixture(scope="module")
+def ragged():
+    """Seven orbitals on a ragged 12 x 15 x 10 grid with a random pair mask."""
+    spec = synth.small_spec(n=12, n_orb=7, L=8.5, seed=33)
+    sysm = synth.build_system(spec)
+    rng = np.random.default_rng(77)
+    phi = np.stack([np.resize(f, (12, 15, 10)) for f in sysm.phi])
+    cell = _ortho((8.5, 10.0, 7.5))
+    mask = np.triu(rng.random((7, 7)) < 0.6)
+    return phi, cell, mask
+
+
+def test_rows_of_eq2_pinned_to_apply_vx(ragged):
+    """The row form of Eq. (2) (used for sampled and full-array references)
+    equals the pinned unordered-pair loop, with and without a pair mask, and
+    its column split adds back to the whole row."""
+    phi, cell, mask = ragged
+    rows = [0, 3, 6]
+    for m in (None, mask):
+        W = O.apply_vx(phi, cell, ALPHA, pair_mask=m)
+        Wr = O.apply_vx_rows(phi, cell, ALPHA, rows, pair_mask=m)
+        for a, i in enumerate(rows):
+            assert O.rel_err(Wr[a], W[i]) < 1e-13
+        split = (O.apply_vx_rows(phi, cell, ALPHA, rows, pair_mask=m, cols=range(0, 7, 2))
+                 + O.apply_vx_rows(phi, cell, ALPHA, rows, pair_mask=m, cols=range(1, 7, 2)))
+        assert O.rel_err(split, Wr) < 1e-13
+
+
+def test_row_of_eq2_matches_explicit_dft():
+    """One row against the explicit-DFT route of P1 (all j, masked j)."""
+    n, lengths = 8, (6.0, 7.0, 8.0)
+    shape = (n, n, n)
+    rng = np.random.default_rng(9)
+    phi = rng.standard_normal((4,) + shape)
+    mask = np.triu(np.ones((4, 4), bool))
+    mask[1, 3] = False
+    F = _brute_dft(shape)
+    for m in (None, mask):
+        ref = np.zeros(shape)
+        for j in range(4):
+            if m is not None and not m[min(1, j), max(1, j)]:
+                continue
+            ref -= ALPHA * _brute_potential(phi[1] * phi[j], lengths, F).real * phi[j]
+        got = O.apply_vx_rows(phi, _ortho(lengths), ALPHA, [1], pair_mask=m)[0]
+        assert O.rel_err(got, ref) < 1e-12
+
+
+def test_row_pools_pinned_to_apply_vx(ragged):
+    """The process-pool drivers of the row form (few rows: split over j;
+    many rows: one row per task; all rows) give the pinned W."""
+    from oracle import pool
+    phi, cell, mask = ragged
+    for m in (None, mask):
+        W = O.apply_vx(phi, cell, ALPHA, pair_mask=m)
+        few = pool.apply_vx_rows_pool(phi, cell, ALPHA, [2, 5], processes=3, pair_mask=m)
+        many = pool.apply_vx_rows_pool(phi, cell, ALPHA, [0, 1, 4, 6], processes=2,
+                                       pair_mask=m)
+        for i, w in list(few.items()) + list(many.items()):
+            assert O.rel_err(w, W[i]) < 1e-13
+        assert O.rel_err(pool.apply_vx_pool(phi, cell, ALPHA, 3, pair_mask=m), W) < 1e-13
+
+
 def test_overlap_screen_matches_direct_integral(small):
     spec, sysm, out = small
     mask, S = O.overlap_screen(sysm.phi, sysm.dV, 0.05)
