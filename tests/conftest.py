@@ -39,6 +39,8 @@ def _job_processes():
 def pytest_collection_finish(session):
     """Start the oracle references the selected full-size GPU tests need, in a
     separate process, before any test initialises the GPU."""
+    if session.config.option.collectonly:
+        return
     tasks = []
     for item in session.items:
         for t in _JOB_TASKS.get(os.path.basename(str(item.fspath)), []):
