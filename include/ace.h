@@ -114,6 +114,23 @@ int ace_build(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes, con
 int ace_apply(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes, const double *xi,
               const double *psi, int n_vec, double *out);
 
+/* ace_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same result as ace_apply (up to rounding: the split-K products may be
+ * split into fewer partials) with no workspace argument.  Its scratch, the
+ * n_vec x n_orb coefficients and their split-K partial products, lives in a
+ * static device array of ACE_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every device it runs on until the process ends; the call itself allocates
+ * nothing (no hipMalloc, no allocating library routine).  Returns
+ * ACE_ERR_SIZE (before any device work) when the coefficients and one
+ * partial product, 8 n_vec n_orb bytes each (the first rounded up to a
+ * multiple of 256), exceed that size, and the argument errors of ace_apply.  Every call on one device shares that device's array and leaves
+ * its contents behind: calls that overlap in time on one device (different
+ * streams or threads) race and must be serialised by the caller. */
+#define ACE_NOALLOC_SCRATCH_BYTES (32u << 20)
+int ace_apply_noalloc(const ace_plan *plan, void *stream, const double *xi, const double *psi,
+                      int n_vec, double *out);
+
 /* E_x = -alpha sum_{i<=j} (2 - delta_ij) (ij|ji) with
  * (ij|ji) = (Omega / N^2) sum_m K(m) |FFT(phi_i phi_j)(m)|^2.
  *   pair_mask as in ace_build.

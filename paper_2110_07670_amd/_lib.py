@@ -27,7 +27,7 @@ EXPORTS = ["ace_plan_create", "ace_plan_destroy", "ace_workspace_bytes",
            "ace_plan_set_tiling", "ace_plan_set_schedule", "ace_overlap_integrals", "ace_wannier", "ace_mlp_screen",
            "ace_mlp_weight_count", "ace_batch_create", "ace_batch_destroy",
            "ace_batch_workspace_bytes", "ace_batch_build", "scdm_workspace_bytes",
-           "scdm_preselect", "scdm_localize"]
+           "scdm_preselect", "scdm_localize", "ace_apply_noalloc"]
 PROBE_EXPORTS = ["ace_bandwidth_probe"]
 PROBE_KINDS = {"read_write": 0, "read": 1, "write": 2}
 ACE_BATCH_MAX = 1024
@@ -112,6 +112,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.scdm_preselect.restype = i
     lib.scdm_localize.argtypes = [vp, vp, vp, sz, vp, vp, i, vp, vp, vp]
     lib.scdm_localize.restype = i
+    lib.ace_apply_noalloc.argtypes = [vp, vp, vp, vp, i, vp]
+    lib.ace_apply_noalloc.restype = i
     lib.ace_bandwidth_probe.argtypes = [i, vp, vp, sz, i]
     lib.ace_bandwidth_probe.restype = i
     _LIB = lib
@@ -311,6 +313,21 @@ def apply_into(plan: Plan, xi, psi, out, ws, stream=None):
     rc = load().ace_apply(plan.handle, _stream(stream), _ptr(ws), ws.numel() * ws.element_size(),
                           _ptr(xi), _ptr(psi), n_vec, _ptr(out))
     _check(rc, "ace_apply")
+
+
+def apply_noalloc_into(plan: Plan, xi, psi, out, stream=None):
+    """ace_apply_noalloc: the apply with the library's static scratch (no
+    workspace, no allocation in the library)."""
+    plan.check_orbitals(xi, "xi", cuda=False)
+    if not hasattr(psi, "shape") or psi.dim() != 4 or int(psi.shape[0]) < 1:
+        raise ValueError("psi must be a (n_vec, n1, n2, n3) tensor")
+    n_vec = int(psi.shape[0])
+    plan.check_orbitals(psi, "psi", count=n_vec, cuda=False)
+    plan.check_orbitals(out, "out", count=n_vec, cuda=False)
+    _on_device(None, ("xi", xi), ("psi", psi), ("out", out))
+    rc = load().ace_apply_noalloc(plan.handle, _stream(stream), _ptr(xi), _ptr(psi), n_vec,
+                                  _ptr(out))
+    _check(rc, "ace_apply_noalloc")
 
 
 def ace_apply(plan: Plan, xi, psi, ws=None, stream=None):

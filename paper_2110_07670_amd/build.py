@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libacex.so")
-SOURCES = ["poisson.hip", "dense.hip", "screen.hip", "scdm.hip", "probe.hip", "api.cpp"]
+SOURCES = ["poisson.hip", "dense.hip", "screen.hip", "scdm.hip", "probe.hip", "noalloc.hip", "api.cpp"]
 ARCH = "gfx950"
 
 

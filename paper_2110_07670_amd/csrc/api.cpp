@@ -556,6 +556,48 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
 
 }  // namespace
 
+// ------------------------------------------------------------------ the apply, shared
+// by ace_apply (scratch in the caller's workspace) and ace_apply_noalloc
+// (scratch in the library's static device array).
+
+namespace acex {
+
+int apply_check(const ace_plan* p, const double* xi, const double* psi, int n_vec,
+                const double* out) {
+  if (!p || !xi || !psi || !out) return ACE_ERR_ARG;
+  if (n_vec < 1) return ACE_ERR_ARG;
+  const size_t xi_bytes = (size_t)p->n_orb * p->npts * sizeof(double);
+  const size_t v_bytes = (size_t)n_vec * p->npts * sizeof(double);
+  if (overlaps(out, v_bytes, xi, xi_bytes) || overlaps(out, v_bytes, psi, v_bytes))
+    return ACE_ERR_ARG;
+  return ACE_OK;
+}
+
+int apply_splits(const ace_plan* p, int n_vec) {
+  return gemm_abt_splits(n_vec, p->n_orb, p->npts);
+}
+
+int apply_orbitals(const ace_plan* p) { return p->n_orb; }
+
+int apply_enqueue(const ace_plan* p, hipStream_t s, double* C, double* part, int ns,
+                  const double* xi, const double* psi, int n_vec, double* out) {
+  ProfScope ps(p, 8, s);
+  // C[v][k] = dV <psi_v, xi_k>
+  hipError_t e = launch_gemm_abt(psi, xi, n_vec, p->n_orb, p->npts, p->dV, C, part, ns, false,
+                                 nullptr, s);
+  if (e != hipSuccess) return hip_fail(e);
+  // out[v] = -sum_k C[v][k] xi_k
+  e = launch_gemm_ab(C, xi, n_vec, p->n_orb, p->npts, -1.0, out, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e);
+  return ACE_OK;
+}
+
+int apply_device_present() { return device_present(); }
+
+int apply_hip_fail(hipError_t e) { return hip_fail(e); }
+
+}  // namespace acex
+
 // ====================================================================== C-ABI
 
 extern "C" {
@@ -687,28 +729,16 @@ int ace_build(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const 
 
 int ace_apply(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const double* xi,
               const double* psi, int n_vec, double* out) {
-  if (!p || !ws || !xi || !psi || !out) return ACE_ERR_ARG;
-  if (n_vec < 1) return ACE_ERR_ARG;
-  const size_t xi_bytes = (size_t)p->n_orb * p->npts * sizeof(double);
-  const size_t v_bytes = (size_t)n_vec * p->npts * sizeof(double);
-  if (overlaps(out, v_bytes, xi, xi_bytes) || overlaps(out, v_bytes, psi, v_bytes))
-    return ACE_ERR_ARG;
+  int rc = acex::apply_check(p, xi, psi, n_vec, out);
+  if (rc != ACE_OK) return rc;
+  if (!ws) return ACE_ERR_ARG;
   if (ws_bytes < ace_apply_workspace_bytes(p, n_vec)) return ACE_ERR_WORKSPACE;
   if (!device_present()) return ACE_ERR_NODEV;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   double* C = reinterpret_cast<double*>(w);
   double* part = reinterpret_cast<double*>(w + align256((size_t)n_vec * p->n_orb * sizeof(double)));
-  const int ns = acex::gemm_abt_splits(n_vec, p->n_orb, p->npts);
-  ProfScope ps(p, 8, s);
-  // C[v][k] = dV <psi_v, xi_k>
-  hipError_t e = acex::launch_gemm_abt(psi, xi, n_vec, p->n_orb, p->npts, p->dV, C, part, ns,
-                                       false, nullptr, s);
-  if (e != hipSuccess) return hip_fail(e);
-  // out[v] = -sum_k C[v][k] xi_k
-  e = acex::launch_gemm_ab(C, xi, n_vec, p->n_orb, p->npts, -1.0, out, nullptr, s);
-  if (e != hipSuccess) return hip_fail(e);
-  return ACE_OK;
+  return acex::apply_enqueue(p, static_cast<hipStream_t>(stream), C, part,
+                             acex::apply_splits(p, n_vec), xi, psi, n_vec, out);
 }
 
 int exx_energy(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const double* phi,

@@ -142,3 +142,20 @@ hipError_t launch_scdm_polar(const double* phi, const int* pivots, int k, int64_
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 
 }  // namespace acex
+
+// The apply stage of the host runtime (api.cpp), shared by the entry points
+// that take their scratch from the caller's workspace and from the library's
+// static array.  apply_check validates on the host (ACE_OK or a status);
+// apply_enqueue launches C = dV psi xi^T (split over K into ns fixed-order
+// partials held in part[ns][n_vec][n_orb]) and out = -C xi on stream s.
+struct ace_plan;
+namespace acex {
+int apply_check(const ace_plan* p, const double* xi, const double* psi, int n_vec,
+                const double* out);
+int apply_splits(const ace_plan* p, int n_vec);
+int apply_orbitals(const ace_plan* p);
+int apply_enqueue(const ace_plan* p, hipStream_t s, double* C, double* part, int ns,
+                  const double* xi, const double* psi, int n_vec, double* out);
+int apply_device_present();
+int apply_hip_fail(hipError_t e);
+}  // namespace acex
