@@ -670,11 +670,17 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
     q0 += ga;
     lds_barrier();
   }
+  // all B rows of W are read before any is written: a store followed by the
+  // next row's load would have to wait for that load (the compiler cannot
+  // tell the rows apart), one memory round trip per row
+  double wold[B];
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const int64_t ob = (int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r;
-    __builtin_nontemporal_store(__builtin_nontemporal_load(&W[ob]) - alpha * acc[b], &W[ob]);
-  }
+  for (int b = 0; b < B; ++b)
+    wold[b] = __builtin_nontemporal_load(&W[(int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r]);
+#pragma unroll
+  for (int b = 0; b < B; ++b)
+    __builtin_nontemporal_store(wold[b] - alpha * acc[b],
+                                &W[(int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r]);
 }
 
 // ------------------------------------------------------------------ z rows (fallback)
@@ -976,9 +982,15 @@ __global__ __launch_bounds__(kAccThreads) void k_accumulate(
     if constexpr (DIAG) sacc[cur][t] = accA;
     else w_sub(&W[(int64_t)orbs[cur] * npts + r], alpha * accA);
   }
+  // the other side's rows: all read before any is written (one round trip)
+  double wold[B];
 #pragma unroll
   for (int b = 0; b < B; ++b)
-    if ((use >> b) & 1u) w_sub(&W[(int64_t)side[b] * npts + r], alpha * sacc[b][t]);
+    wold[b] = ((use >> b) & 1u) ? __builtin_nontemporal_load(&W[(int64_t)side[b] * npts + r]) : 0.0;
+#pragma unroll
+  for (int b = 0; b < B; ++b)
+    if ((use >> b) & 1u)
+      __builtin_nontemporal_store(wold[b] - alpha * sacc[b][t], &W[(int64_t)side[b] * npts + r]);
 }
 
 template <typename TS, int B, bool DIAG>
@@ -1024,11 +1036,19 @@ __global__ __launch_bounds__(256) void k_accumulate_full(
       }
     });
   });
+  // every W row read before any is written (one round trip, not one per row)
+  double wI[B], wJ[DIAG ? 1 : B];
 #pragma unroll
-  for (int a = 0; a < B; ++a) W[(int64_t)orbs[a] * npts + r] -= alpha * accI[a];
+  for (int a = 0; a < B; ++a) wI[a] = W[(int64_t)orbs[a] * npts + r];
   if constexpr (!DIAG) {
 #pragma unroll
-    for (int b = 0; b < B; ++b) W[(int64_t)orbs[B + b] * npts + r] -= alpha * accJ[b];
+    for (int b = 0; b < B; ++b) wJ[b] = W[(int64_t)orbs[B + b] * npts + r];
+  }
+#pragma unroll
+  for (int a = 0; a < B; ++a) W[(int64_t)orbs[a] * npts + r] = wI[a] - alpha * accI[a];
+  if constexpr (!DIAG) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) W[(int64_t)orbs[B + b] * npts + r] = wJ[b] - alpha * accJ[b];
   }
 }
 
