@@ -197,12 +197,16 @@ RHO_CUT = {2: 2.5e-2, 3: 1e-2, 5: 2e-3}  # the paper's Table 3 by system size
 
 
 def run_screened(args):
-    """Screened build vs all-pairs build on one workload (default config 5).
+    """Screened build vs all-pairs builds on one workload (default config 5).
 
-    A screened step = Wannier moments + MLP pair predictions (or the overlap
-    integrals) + the host mask + ace_build(mask) + ace_apply.  The MLP is
-    trained beforehand (not timed) on pair energies the GPU build produces for
-    the training systems.  E_x error is judged against the all-pairs build."""
+    A screened step = the library's screening decision (ace_screen_mask:
+    overlap integrals, or Wannier moments + MLP pair predictions, on the GPU,
+    then the mask on the host, with the all-pairs fallback) + ace_build(mask)
+    + ace_apply.  The MLP is trained beforehand (not timed) on pair energies
+    the GPU build produces for the training systems.  Timed beside it, on the
+    same inputs: the all-pairs build in the screened run's bulk precision and
+    the plain FP64 all-pairs build (the reference form); E_x errors are
+    judged against the FP64 all-pairs build."""
     import numpy as np
     import torch
 
@@ -211,8 +215,8 @@ def run_screened(args):
     cfg = args.config if args.config != 2 else 5
     spec = synth.config(cfg)
     system = synth.build_system(spec)
-    params = None
     dev = torch.device("cuda:0")
+    wts = None
     t_train = 0.0
     if args.screen == "mlp":
         t0 = time.perf_counter()
@@ -221,9 +225,25 @@ def run_screened(args):
         t_train = time.perf_counter() - t0
         wts = torch.from_numpy(screening.weights_to_array(params)).to(dev)
     phi = torch.from_numpy(system.phi).to(dev)
-    plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, args.precision, spec.alpha)
-    if args.tiling:
-        plan.set_tiling(*[int(v) for v in args.tiling.split(",")])
+    budget = 1e-6 * spec.n_atoms
+    rho_cut = RHO_CUT.get(cfg, 2e-3)
+
+    def make(precision):
+        plan = _lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, precision, spec.alpha)
+        if args.tiling:
+            plan.set_tiling(*[int(v) for v in args.tiling.split(",")])
+        return plan
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    plan = make(args.precision)
     ws = _lib.workspace(plan.workspace_bytes(), dev)
     ws_apply = _lib.workspace(plan.apply_workspace_bytes(spec.n_orb), dev)
     W = torch.empty_like(phi)
@@ -232,41 +252,23 @@ def run_screened(args):
     M = torch.empty((spec.n_orb, spec.n_orb), dtype=torch.float64, device=dev)
     ex = torch.zeros(1, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
-    budget = 1e-6 * spec.n_atoms
+    state = {}
 
-    def full_step():
-        _lib.build_into(plan, phi, W, M, xi, ex, info, ws)
-        _lib.apply_into(plan, xi, phi, out, ws_apply)
+    def full_step(pl=plan, w=ws):
+        _lib.build_into(pl, phi, W, M, xi, ex, info, w)
+        _lib.apply_into(pl, xi, phi, out, ws_apply)
 
     def screened_step():
-        if args.screen == "mlp":
-            _, feat = _lib.wannier(plan, phi)
-            pred = _lib.mlp_screen(plan, feat, wts).cpu().numpy()
-            mask = screening.mask_by_budget(pred, budget)
-        else:
-            S = _lib.overlap_integrals(plan, phi, ws).cpu().numpy()
-            mask = screening.overlap_mask(S, RHO_CUT.get(cfg, 2e-3))
+        mask, rep = _lib.screen_mask(plan, phi, args.screen, rho_cut=rho_cut, budget=budget,
+                                     weights=wts, ws=ws)
         _lib.build_into(plan, phi, W, M, xi, ex, info, ws, pair_mask=mask)
         _lib.apply_into(plan, xi, phi, out, ws_apply)
-        return mask
+        state["mask"], state["rep"] = mask, rep
 
-    full_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        full_step()
-    torch.cuda.synchronize()
-    t_full = (time.perf_counter() - t0) / args.steps
+    t_full = timed(full_step, args.steps)
     e_full = float(ex.item())
-    mask = screened_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        mask = screened_step()
-    torch.cuda.synchronize()
-    t_scr = (time.perf_counter() - t0) / args.steps
+    t_scr = timed(screened_step, args.steps)
     e_scr = float(ex.item())
-    kept = int(mask.sum())
     stages = {}
     for label, fn in (("screened", screened_step), ("all_pairs", full_step)):
         plan.set_profiling(True)
@@ -274,18 +276,36 @@ def run_screened(args):
         torch.cuda.synchronize()
         stages[label] = {k: [round(ms, 3), c] for k, (ms, c) in plan.profile_read().items() if c}
         plan.set_profiling(False)
+    t_fp64, e_fp64 = None, None
+    if args.precision != "fp64" and not args.no_fp64_reference:
+        del ws
+        torch.cuda.empty_cache()
+        plan64 = make("fp64")
+        ws64 = _lib.workspace(plan64.workspace_bytes(), dev)
+        t_fp64 = timed(lambda: full_step(plan64, ws64), max(1, min(args.steps, 2)))
+        e_fp64 = float(ex.item())
+        del ws64
+    elif args.precision == "fp64":
+        t_fp64, e_fp64 = t_full, e_full
+    kept = int(state["mask"].sum())
+    e_ref = e_fp64 if e_fp64 is not None else e_full
     result = {
-        "metric": "screened ACE build vs all-pairs build (%s screen)" % args.screen,
+        "metric": "screened ACE build vs all-pairs builds (%s screen)" % args.screen,
         "value": spec.n_pairs / t_scr, "unit": "pairs covered/s",
         "solves_per_s": kept / t_scr, "all_pairs_value": spec.n_pairs / t_full,
-        "speedup": t_full / t_scr, "ms_per_step": 1000 * t_scr, "all_pairs_ms": 1000 * t_full,
-        "pairs_kept": kept, "pairs_total": spec.n_pairs,
-        "ex_all_pairs": e_full, "ex_screened": e_scr, "ex_error_Ha": abs(e_scr - e_full),
-        "ex_error_Ha_per_atom": abs(e_scr - e_full) / spec.n_atoms, "budget_Ha": budget,
-        "train_s": t_train, "steps": args.steps, "n_gpus": 1, "stages_ms_launches": stages,
+        "speedup_vs_all_pairs_same_precision": t_full / t_scr,
+        "speedup_vs_fp64_all_pairs": (t_fp64 / t_scr) if t_fp64 else None,
+        "ms_per_step": 1000 * t_scr, "all_pairs_ms": 1000 * t_full,
+        "fp64_all_pairs_ms": 1000 * t_fp64 if t_fp64 else None,
+        "pairs_kept": kept, "pairs_total": spec.n_pairs, "screen_report": state["rep"],
+        "ex_fp64_all_pairs": e_fp64, "ex_all_pairs": e_full, "ex_screened": e_scr,
+        "ex_error_Ha_per_atom_vs_fp64": abs(e_scr - e_ref) / spec.n_atoms,
+        "ex_error_Ha_per_atom_all_pairs_same_precision_vs_fp64": abs(e_full - e_ref) / spec.n_atoms,
+        "budget_Ha": budget, "train_s": t_train, "steps": args.steps, "n_gpus": 1,
+        "stages_ms_launches": stages,
         "dtype": "f64" if args.precision == "fp64" else "f32 transforms, f64 W/M/Cholesky/E",
         "config": {"workload": workload_text(spec, args.precision), "n_orb": spec.n_orb,
-                   "grid": spec.n, "rho_cut": RHO_CUT.get(cfg) if args.screen == "overlap" else None},
+                   "grid": spec.n, "rho_cut": rho_cut if args.screen == "overlap" else None},
     }
     print(json.dumps(result), flush=True)
 
@@ -476,7 +496,9 @@ def main():
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the streaming-probe measurement of the achievable HBM rates")
     ap.add_argument("--screen", choices=["mlp", "overlap"], default=None,
-                    help="measure a screened build against the all-pairs build instead")
+                    help="measure a screened build against the all-pairs builds instead")
+    ap.add_argument("--no-fp64-reference", action="store_true",
+                    help="--screen: skip timing the plain FP64 all-pairs build")
     args = ap.parse_args()
     if args.precision is None:
         cfg = 5 if args.screen and args.config == 2 else args.config  # the screened default

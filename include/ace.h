@@ -168,6 +168,60 @@ int ace_mlp_screen(const ace_plan *plan, void *stream, const double *feat, const
                    float *pred);
 int ace_mlp_weight_count(void);
 
+/* The screening decision (section "s-MTACE Method"): which pairs ace_build
+ * skips, from the overlap integrals or from the learned pair-energy
+ * predictions, with the all-pairs build as the fallback.
+ *
+ * ace_screen_desc:
+ *   kind        ACE_SCREEN_OVERLAP: keep (i, j) when S_ij >= rho_cut (the
+ *               paper's criterion, S as from ace_overlap_integrals);
+ *               ACE_SCREEN_MLP: skip the pairs of smallest predicted |e_ij|,
+ *               in increasing order, while their predicted sum stays at most
+ *               budget / safety (predictions as from ace_mlp_screen, read as
+ *               log10 of the expected |e_ij| in Ha).
+ *   rho_cut     overlap threshold (ACE_SCREEN_OVERLAP).
+ *   budget      Ha: the largest exchange energy the skipped pairs may carry.
+ *   safety      >= 1; the MLP screen keeps the predicted skipped energy at
+ *               most budget / safety.
+ *   mlp_weights device float[ace_mlp_weight_count()] or NULL.  Required for
+ *               ACE_SCREEN_MLP; with ACE_SCREEN_OVERLAP, when given, the
+ *               predicted energy of the skipped pairs is reported and checked
+ *               against the budget.
+ * ace_screen_report: kept and total unordered pairs, the predicted energy of
+ *   the skipped pairs (Ha; NaN without weights) and fallback = 1 when that
+ *   prediction exceeds the budget, in which case the mask keeps every pair.
+ * Diagonal pairs are always kept.  The mask is host [n_orb][n_orb] uint8,
+ * upper triangle written (i <= j), the rest zero, ready for ace_build.
+ *
+ * ace_screen_mask: computes the inputs on the device (in the ace_build
+ *   workspace), copies them to the host and decides; it synchronises
+ *   `stream`.
+ * ace_screen_mask_host: the decision alone from host arrays S ([n][n]
+ *   double, or NULL for ACE_SCREEN_MLP) and pred ([n][n] float, upper
+ *   triangle read; NULL when no predictions are available).  Touches no
+ *   device.  ACE_ERR_ARG for a null mask, report or desc, n < 1, an unknown
+ *   kind, a missing input for the kind, budget < 0 or safety < 1. */
+#define ACE_SCREEN_OVERLAP 0
+#define ACE_SCREEN_MLP 1
+typedef struct {
+  int kind;
+  double rho_cut;
+  double budget;
+  double safety;
+  const float *mlp_weights;
+} ace_screen_desc;
+typedef struct {
+  int64_t pairs_kept;
+  int64_t pairs_total;
+  double predicted_skipped;
+  int fallback;
+} ace_screen_report;
+int ace_screen_mask(const ace_plan *plan, void *stream, void *ws, size_t ws_bytes,
+                    const double *phi, const ace_screen_desc *desc, uint8_t *mask,
+                    ace_screen_report *report);
+int ace_screen_mask_host(int n_orb, const ace_screen_desc *desc, const double *S,
+                         const float *pred, uint8_t *mask, ace_screen_report *report);
+
 /* Static text for a status code. */
 const char *ace_error_string(int code);
 /* The hipError_t behind the calling thread's last ACE_ERR_HIP (0 if none). */

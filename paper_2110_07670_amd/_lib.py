@@ -27,7 +27,8 @@ EXPORTS = ["ace_plan_create", "ace_plan_destroy", "ace_workspace_bytes",
            "ace_plan_set_tiling", "ace_plan_set_schedule", "ace_overlap_integrals", "ace_wannier", "ace_mlp_screen",
            "ace_mlp_weight_count", "ace_batch_create", "ace_batch_destroy",
            "ace_batch_workspace_bytes", "ace_batch_build", "scdm_workspace_bytes",
-           "scdm_preselect", "scdm_localize", "ace_apply_noalloc"]
+           "scdm_preselect", "scdm_localize", "ace_apply_noalloc", "ace_screen_mask",
+           "ace_screen_mask_host"]
 PROBE_EXPORTS = ["ace_bandwidth_probe"]
 PROBE_KINDS = {"read_write": 0, "read": 1, "write": 2}
 ACE_BATCH_MAX = 1024
@@ -41,6 +42,19 @@ class AceError(RuntimeError):
         if code == ACE_ERR_HIP:
             msg += " (hipError %d)" % _LIB.ace_last_hip_error()
         super().__init__(msg)
+
+
+class ScreenDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("rho_cut", ctypes.c_double), ("budget", ctypes.c_double),
+                ("safety", ctypes.c_double), ("mlp_weights", ctypes.c_void_p)]
+
+
+class ScreenReport(ctypes.Structure):
+    _fields_ = [("pairs_kept", ctypes.c_int64), ("pairs_total", ctypes.c_int64),
+                ("predicted_skipped", ctypes.c_double), ("fallback", ctypes.c_int)]
+
+
+ACE_SCREEN_OVERLAP, ACE_SCREEN_MLP = 0, 1
 
 
 class AceDesc(ctypes.Structure):
@@ -112,6 +126,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.scdm_preselect.restype = i
     lib.scdm_localize.argtypes = [vp, vp, vp, sz, vp, vp, i, vp, vp, vp]
     lib.scdm_localize.restype = i
+    lib.ace_screen_mask.argtypes = [vp, vp, vp, sz, vp, ctypes.POINTER(ScreenDesc), vp,
+                                    ctypes.POINTER(ScreenReport)]
+    lib.ace_screen_mask.restype = i
+    lib.ace_screen_mask_host.argtypes = [i, ctypes.POINTER(ScreenDesc), vp, vp, vp,
+                                         ctypes.POINTER(ScreenReport)]
+    lib.ace_screen_mask_host.restype = i
     lib.ace_apply_noalloc.argtypes = [vp, vp, vp, vp, i, vp]
     lib.ace_apply_noalloc.restype = i
     lib.ace_bandwidth_probe.argtypes = [i, vp, vp, sz, i]
@@ -406,6 +426,57 @@ def mlp_screen(plan: Plan, feat, weights, stream=None):
     rc = load().ace_mlp_screen(plan.handle, _stream(stream), _ptr(feat), _ptr(w), _ptr(pred))
     _check(rc, "ace_mlp_screen")
     return pred
+
+
+def _screen_desc(kind: str, rho_cut: float, budget: float, safety: float, weights):
+    d = ScreenDesc()
+    d.kind = {"overlap": ACE_SCREEN_OVERLAP, "mlp": ACE_SCREEN_MLP}[kind]
+    d.rho_cut, d.budget, d.safety = float(rho_cut), float(budget), float(safety)
+    d.mlp_weights = _ptr(weights) if weights is not None else None
+    return d
+
+
+def _report(rep: ScreenReport):
+    return {"pairs_kept": int(rep.pairs_kept), "pairs_total": int(rep.pairs_total),
+            "predicted_skipped": float(rep.predicted_skipped), "fallback": bool(rep.fallback)}
+
+
+def screen_mask(plan: Plan, phi, kind: str, rho_cut: float = 0.0, budget: float = 0.0,
+                safety: float = 2.0, weights=None, ws=None, stream=None):
+    """ace_screen_mask: (host uint8 [n_orb, n_orb] pair mask, report dict)."""
+    plan.check_orbitals(phi)
+    if weights is not None:
+        _tensor(weights, "weights", (mlp_weight_count(),), "float32", device=phi.device)
+    if ws is None:
+        ws = workspace(plan.workspace_bytes(), phi.device)
+    _tensor(ws, "ws", None, None, device=phi.device, min_bytes=plan.workspace_bytes())
+    mask = np.zeros((plan.n_orb, plan.n_orb), dtype=np.uint8)
+    rep = ScreenReport()
+    d = _screen_desc(kind, rho_cut, budget, safety, weights)
+    rc = load().ace_screen_mask(plan.handle, _stream(stream), _ptr(ws),
+                                ws.numel() * ws.element_size(), _ptr(phi), ctypes.byref(d),
+                                mask.ctypes.data, ctypes.byref(rep))
+    _check(rc, "ace_screen_mask")
+    return mask, _report(rep)
+
+
+def screen_mask_host(kind: str, S=None, pred=None, rho_cut: float = 0.0, budget: float = 0.0,
+                     safety: float = 2.0):
+    """ace_screen_mask_host on host arrays (no device)."""
+    n = int((S if S is not None else pred).shape[0])
+    Sa = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
+    Pa = None if pred is None else np.ascontiguousarray(pred, dtype=np.float32)
+    for a in (Sa, Pa):
+        if a is not None and a.shape != (n, n):
+            raise ValueError("screening inputs must be (n, n)")
+    mask = np.zeros((n, n), dtype=np.uint8)
+    rep = ScreenReport()
+    d = _screen_desc(kind, rho_cut, budget, safety, None)
+    rc = load().ace_screen_mask_host(n, ctypes.byref(d), None if Sa is None else Sa.ctypes.data,
+                                     None if Pa is None else Pa.ctypes.data, mask.ctypes.data,
+                                     ctypes.byref(rep))
+    _check(rc, "ace_screen_mask_host")
+    return mask, _report(rep)
 
 
 # ------------------------------------------------------------------ batches

@@ -123,7 +123,11 @@ void layout(ace_plan* p) {
   p->off_phi32 = off;
   if (p->prec == 1) off += align256((size_t)p->n_orb * p->npts * sizeof(float));
   p->off_S = off;
-  off += p->s_grid_bytes * (size_t)p->max_pack_tile;
+  // the transform scratch also holds the screening inputs of ace_screen_mask
+  const size_t nn = (size_t)p->n_orb * p->n_orb;
+  const size_t screen_bytes = nn * sizeof(double) + (size_t)p->n_orb * 10 * sizeof(double) +
+                              nn * sizeof(float);
+  off += std::max(p->s_grid_bytes * (size_t)p->max_pack_tile, align256(screen_bytes));
   p->off_part = off;
   off += align256((size_t)p->nsplit * p->n_orb * p->n_orb * sizeof(double));
   p->off_L = off;
@@ -860,6 +864,109 @@ int ace_mlp_screen(const ace_plan* p, void* stream, const double* feat, const fl
   const hipError_t e = acex::launch_mlp_pairs(feat, p->n_orb, p->L, weights, pred, s);
   if (e != hipSuccess) return hip_fail(e);
   return ACE_OK;
+}
+
+// ------------------------------------------------------------------ screening decision
+
+int ace_screen_mask_host(int n, const ace_screen_desc* d, const double* S, const float* pred,
+                         uint8_t* mask, ace_screen_report* rep) {
+  if (!d || !mask || !rep || n < 1) return ACE_ERR_ARG;
+  if (d->kind != ACE_SCREEN_OVERLAP && d->kind != ACE_SCREEN_MLP) return ACE_ERR_ARG;
+  if (!(d->budget >= 0.0) || !(d->safety >= 1.0)) return ACE_ERR_ARG;
+  if (d->kind == ACE_SCREEN_OVERLAP && !S) return ACE_ERR_ARG;
+  if (d->kind == ACE_SCREEN_MLP && !pred) return ACE_ERR_ARG;
+  const size_t nn = (size_t)n * n;
+  std::memset(mask, 0, nn);
+  for (int i = 0; i < n; ++i) mask[(size_t)i * n + i] = 1;
+  // predicted |e_ij| of the off-diagonal pairs, upper triangle in row order
+  auto energy = [&](int i, int j) { return std::pow(10.0, (double)pred[(size_t)i * n + j]); };
+  double skipped = 0.0;
+  if (d->kind == ACE_SCREEN_OVERLAP) {
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) {
+        if (S[(size_t)i * n + j] >= d->rho_cut) mask[(size_t)i * n + j] = 1;
+        else if (pred) skipped += energy(i, j);
+      }
+  } else {
+    std::vector<std::pair<double, int64_t>> e;
+    e.reserve((size_t)n * (n - 1) / 2);
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) e.push_back({energy(i, j), (int64_t)i * n + j});
+    // smallest first; ties in row order
+    std::stable_sort(e.begin(), e.end(),
+                     [](const std::pair<double, int64_t>& x, const std::pair<double, int64_t>& y) {
+                       return x.first < y.first;
+                     });
+    const double limit = d->budget / d->safety;
+    size_t k = 0;
+    for (; k < e.size(); ++k) {
+      if (skipped + e[k].first > limit) break;
+      skipped += e[k].first;
+    }
+    for (size_t q = k; q < e.size(); ++q) mask[e[q].second] = 1;
+  }
+  rep->pairs_total = (int64_t)n * (n + 1) / 2;
+  rep->predicted_skipped = pred ? skipped : std::nan("");
+  rep->fallback = (pred && skipped > d->budget) ? 1 : 0;
+  if (rep->fallback)
+    for (int i = 0; i < n; ++i)
+      for (int j = i; j < n; ++j) mask[(size_t)i * n + j] = 1;
+  int64_t kept = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) kept += mask[(size_t)i * n + j];
+  rep->pairs_kept = kept;
+  return ACE_OK;
+}
+
+int ace_screen_mask(const ace_plan* p, void* stream, void* ws, size_t ws_bytes, const double* phi,
+                    const ace_screen_desc* d, uint8_t* mask, ace_screen_report* rep) {
+  if (!p || !ws || !phi || !d || !mask || !rep) return ACE_ERR_ARG;
+  if (d->kind != ACE_SCREEN_OVERLAP && d->kind != ACE_SCREEN_MLP) return ACE_ERR_ARG;
+  if (d->kind == ACE_SCREEN_MLP && !d->mlp_weights) return ACE_ERR_ARG;
+  if (!(d->budget >= 0.0) || !(d->safety >= 1.0)) return ACE_ERR_ARG;
+  if (ws_bytes < p->total) return ACE_ERR_WORKSPACE;
+  if (!device_present()) return ACE_ERR_NODEV;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  const int n = p->n_orb;
+  const size_t nn = (size_t)n * n;
+  // inputs in the transform scratch: S [n][n] double, z [n][6], feat [n][4], pred [n][n] float
+  double* dS = reinterpret_cast<double*>(w + p->off_S);
+  double* dz = dS + nn;
+  double* dfeat = dz + (size_t)n * 6;
+  float* dpred = reinterpret_cast<float*>(dfeat + (size_t)n * 4);
+  hipError_t e;
+  if (d->kind == ACE_SCREEN_OVERLAP) {
+    e = acex::launch_gemm_abt(phi, phi, n, n, p->npts, p->dV, dS,
+                              reinterpret_cast<double*>(w + p->off_part), p->nsplit, true, nullptr,
+                              s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (d->mlp_weights) {
+    e = acex::launch_moments(phi, p->n, n, p->npts, p->dV, dz, s);
+    if (e != hipSuccess) return hip_fail(e);
+    e = acex::launch_wannier_features(dz, n, p->L, dfeat, s);
+    if (e != hipSuccess) return hip_fail(e);
+    e = acex::launch_mlp_pairs(dfeat, n, p->L, d->mlp_weights, dpred, s);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  std::vector<double> S;
+  std::vector<float> pred;
+  if (d->kind == ACE_SCREEN_OVERLAP) {
+    S.resize(nn);
+    if ((e = hipMemcpyAsync(S.data(), dS, nn * sizeof(double), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return hip_fail(e);
+  }
+  if (d->mlp_weights) {
+    pred.resize(nn);
+    if ((e = hipMemcpyAsync(pred.data(), dpred, nn * sizeof(float), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return hip_fail(e);
+  }
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e);
+  return ace_screen_mask_host(n, d, S.empty() ? nullptr : S.data(),
+                              pred.empty() ? nullptr : pred.data(), mask, rep);
 }
 
 // ------------------------------------------------------------------ batches

@@ -9,7 +9,11 @@ k_probe_rw, whose true traffic is 1 GiB read + 1 GiB written).
 
 Usage: python -m paper_2110_07670_amd.profiling TRACE_DB FETCH_DB WRITE_DB OUT.md "COMMAND"
        python -m paper_2110_07670_amd.profiling --trace-only TRACE_DB OUT.md "TITLE" "COMMAND"
-(the second form: kernel times per kernel and per stage from a trace alone)
+       python -m paper_2110_07670_amd.profiling --counters OUT.md "TITLE" "COMMAND" DB [DB ...]
+(the second form: kernel times per kernel and per stage from a trace alone;
+the third: per-kernel averages of the hardware counters of one or more
+--pmc runs, with the MFMA busy fraction and FP64 matrix rate, and the VALU,
+LDS and wait fractions where those counters were collected)
 """
 from __future__ import annotations
 
@@ -144,8 +148,86 @@ def summarize_trace(trace_db, out_md, title, command):
     return {st: tot / 1e6 for st, (_, tot) in per_stage.items()}
 
 
+# MI355X: 8 XCDs, 256 CUs, 4 SIMDs each; GRBM_GUI_ACTIVE sums the XCDs' cycles
+N_XCD, N_CU, N_SIMD = 8, 256, 1024
+
+
+def counter_table(dbs):
+    """{kernel: {counter: mean per dispatch}, '_dur_us': mean duration}."""
+    out = collections.OrderedDict()
+    for path in dbs:
+        db = sqlite3.connect(path)
+        rows = db.execute("select dispatch_id, kernel_name, counter_name, value, duration "
+                          "from counters_collection").fetchall()
+        per = collections.defaultdict(lambda: collections.defaultdict(dict))
+        for d, k, c, v, dur in rows:
+            per[_short(k)][d][c] = float(v)
+            per[_short(k)][d]["_dur"] = float(dur)
+        for k, disp in per.items():
+            rec = out.setdefault(k, {})
+            cnt = collections.defaultdict(list)
+            for d, cs in disp.items():
+                for c, v in cs.items():
+                    cnt[c].append(v)
+            for c, vs in cnt.items():
+                if c == "_dur":
+                    rec["_dur_us"] = sum(vs) / len(vs) / 1e3
+                    rec["_n"] = len(vs)
+                else:
+                    rec[c] = sum(vs) / len(vs)
+    return out
+
+
+def derived(rec):
+    """Fractions from the raw counters a record holds."""
+    d = {}
+    g = rec.get("GRBM_GUI_ACTIVE")
+    if g:
+        cyc = g / N_XCD  # cycles of the dispatch
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in rec:
+            d["mfma_busy"] = rec["SQ_VALU_MFMA_BUSY_CYCLES"] / (cyc * N_SIMD)
+        if "SQ_INSTS_VALU_MFMA_MOPS_F64" in rec and rec.get("_dur_us"):
+            d["f64_mfma_tflops"] = rec["SQ_INSTS_VALU_MFMA_MOPS_F64"] * 512 / (rec["_dur_us"] * 1e-6) / 1e12
+    w = rec.get("SQ_WAVE_CYCLES")
+    if w:
+        for c, name in (("SQ_WAIT_INST_ANY", "wait_any"), ("SQ_WAIT_INST_LDS", "wait_lds"),
+                        ("SQ_ACTIVE_INST_VALU", "valu_active"), ("SQ_ACTIVE_INST_LDS", "lds_active")):
+            if c in rec:
+                d[name + "_per_wave_cycle"] = rec[c] / w
+    return d
+
+
+def summarize_counters(out_md, title, command, dbs):
+    tab = counter_table(dbs)
+    cols = sorted({c for rec in tab.values() for c in rec if not c.startswith("_")})
+    lines = ["# rocprofv3 counters: %s" % title, "",
+             "Commands (run from the repository root on one MI355X):", "", "```", command, "```", "",
+             "Per-kernel means per dispatch (counters summed over the device as rocprofv3 reports "
+             "them; GRBM_GUI_ACTIVE summed over the 8 XCDs; SQ_* cycle counters in quad-cycles "
+             "where the counter is defined so).", ""]
+    for k, rec in tab.items():
+        lines.append("## %s" % k)
+        lines.append("")
+        lines.append("dispatches %d, mean duration %.1f us" % (rec.get("_n", 0), rec.get("_dur_us", 0.0)))
+        lines.append("")
+        lines.append("| counter | mean |")
+        lines.append("|---|---|")
+        for c in cols:
+            if c in rec:
+                lines.append("| %s | %.4g |" % (c, rec[c]))
+        for name, v in derived(rec).items():
+            lines.append("| %s (derived) | %.3f |" % (name, v))
+        lines.append("")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines))
+    return {k: derived(rec) for k, rec in tab.items()}
+
+
 if __name__ == "__main__":
-    if len(sys.argv) == 6 and sys.argv[1] == "--trace-only":
+    if len(sys.argv) >= 6 and sys.argv[1] == "--counters":
+        print(json.dumps(summarize_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5:]),
+                         indent=1))
+    elif len(sys.argv) == 6 and sys.argv[1] == "--trace-only":
         print(json.dumps(summarize_trace(*sys.argv[2:6]), indent=1))
     elif len(sys.argv) == 6:
         print(json.dumps(summarize(*sys.argv[1:6]), indent=1))

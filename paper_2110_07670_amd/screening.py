@@ -5,16 +5,20 @@ Two screens produce the host `pair_mask` that ace_build takes:
 
 * overlap screen (the paper's criterion): keep (i, j) when
   dV sum_r |phi_i phi_j| >= rho_cut, the integrals from ace_overlap_integrals;
-* learned screen: a 3-64-64-1 ReLU network predicts log10 |e_ij| of the pair
-  energy e_ij = -alpha (2 - delta_ij) (ij|ji) from the minimum-image distance
-  of the two orbitals' Wannier centres and their spreads (ace_wannier +
-  ace_mlp_screen run on the GPU); pairs are skipped smallest-predicted first
-  while the predicted skipped energy stays within a budget.
+* learned screen: a 3-64-64-1 ReLU network predicts log10 of the expected
+  |e_ij| of the pair energy e_ij = -alpha (2 - delta_ij) (ij|ji) from the
+  minimum-image distance of the two orbitals' Wannier centres and their
+  spreads (ace_wannier + ace_mlp_screen run on the GPU); pairs are skipped
+  smallest-predicted first while the predicted skipped energy stays within a
+  budget.
 
-The network is trained here, in numpy, on pair energies and features that
-the GPU build itself produces (exx_energy with per-pair output, ace_wannier)
-for systems drawn by the seeded generators.  The all-pairs build stays both
-the fallback and the judge of the screened result.
+Both decisions are made by the library (ace_screen_mask, through
+_lib.screen_mask), which also falls back to all pairs when the predicted
+energy of the skipped pairs exceeds the budget.  The network is trained
+here, in numpy, on pair energies and features that the GPU build itself
+produces (exx_energy with per-pair output, ace_wannier) for systems drawn by
+the seeded generators.  The all-pairs build stays the judge of the screened
+result.
 """
 from __future__ import annotations
 
@@ -46,11 +50,22 @@ def forward(x: np.ndarray, p: Dict[str, np.ndarray]) -> np.ndarray:
 
 def train_pair_mlp(X: np.ndarray, y: np.ndarray, hidden: int = HIDDEN, epochs: int = 150,
                    batch: int = 2048, lr: float = 2e-3, seed: int = 0,
-                   upper_quantile: float = 0.95) -> Dict[str, np.ndarray]:
+                   calibration: str = "sum", upper_quantile: float = 0.95,
+                   tails=(0.02, 0.05, 0.1, 0.2, 0.35, 0.5)) -> Dict[str, np.ndarray]:
     """Mean-squared error on log10 |e| with Adam (He-initialised ReLU network),
-    then the output bias is raised by the `upper_quantile` of the training
-    residuals, so the prediction bounds log10 |e| from above for that share of
-    pairs (None keeps the mean fit)."""
+    then the output bias is calibrated:
+
+    * "sum" (default): the bias gains the smallest c for which, on the
+      training pairs, sum 10^(f + c) is at least sum 10^y over every tail of
+      smallest predictions (the lowest 2, 5, 10, 20, 35 and 50 % of f): the
+      screen skips such a tail and needs its total, which a mean fit of
+      log10 |e| underestimates by the scatter (the sum is dominated by the
+      pairs that lie above the fit);
+    * "upper": the bias gains the `upper_quantile` of the residuals, so the
+      prediction bounds log10 |e| from above for that share of pairs (a
+      per-pair bound; far more conservative for the sum);
+    * None: the mean fit of log10 |e|.
+    """
     rng = np.random.default_rng(seed)
     mean = X.mean(axis=0)
     std = X.std(axis=0) + 1e-12
@@ -95,8 +110,18 @@ def train_pair_mlp(X: np.ndarray, y: np.ndarray, hidden: int = HIDDEN, epochs: i
                 vh = v[k] / (1 - b2_ ** t)
                 p[k] = p[k] - step_lr * mh / (np.sqrt(vh) + eps)
     p["b3"] = float(p["b3"])
-    if upper_quantile is not None:
-        p["b3"] += float(np.quantile(y - forward(X, p), upper_quantile))
+    res = y - forward(X, p)
+    if calibration == "sum":
+        f = y - res
+        c = -np.inf
+        for t in tails:
+            tail = f <= np.quantile(f, t)
+            c = max(c, float(np.log10(np.sum(10.0 ** y[tail]) / np.sum(10.0 ** f[tail]))))
+        p["b3"] += c
+        p["calibration"] = {"kind": "sum", "shift": c}
+    elif calibration == "upper":
+        p["b3"] += float(np.quantile(res, upper_quantile))
+        p["calibration"] = {"kind": "upper", "quantile": upper_quantile}
     return p
 
 
@@ -148,23 +173,17 @@ def training_data(specs=None, device="cuda:0", floor: float = 1e-12):
 # ------------------------------------------------------------------ masks
 
 def mask_by_budget(pred_log10: np.ndarray, budget: float, safety: float = 2.0) -> np.ndarray:
-    """Keep every pair except the smallest predicted |e_ij|, skipped in increasing
-    order while their predicted sum stays <= budget / safety.  Diagonal pairs
-    are always kept.  pred_log10: [n, n], upper triangle read."""
-    k = pred_log10.shape[0]
-    iu, ju = np.triu_indices(k, 1)
-    e = 10.0 ** pred_log10[iu, ju].astype(np.float64)
-    order = np.argsort(e)
-    csum = np.cumsum(e[order])
-    nskip = int(np.searchsorted(csum, budget / safety, side="right"))
-    mask = np.triu(np.ones((k, k), dtype=bool))
-    sk = order[:nskip]
-    mask[iu[sk], ju[sk]] = False
-    return mask
+    """The learned screen's decision on host predictions (the library's
+    ace_screen_mask_host): skip the smallest predicted |e_ij| while their
+    predicted sum stays <= budget / safety; diagonal pairs always kept."""
+    from . import _lib
+    mask, _ = _lib.screen_mask_host("mlp", pred=pred_log10, budget=budget, safety=safety)
+    return mask.astype(bool)
 
 
 def overlap_mask(S: np.ndarray, rho_cut: float) -> np.ndarray:
-    """The s-MTACE screen: keep (i, j), i <= j, when dV sum |phi_i phi_j| >= rho_cut."""
-    m = np.triu(np.asarray(S) >= rho_cut)
-    np.fill_diagonal(m, True)
-    return m
+    """The s-MTACE screen on host integrals (the library's ace_screen_mask_host):
+    keep (i, j), i <= j, when dV sum |phi_i phi_j| >= rho_cut."""
+    from . import _lib
+    mask, _ = _lib.screen_mask_host("overlap", S=S, rho_cut=rho_cut, budget=float("inf"))
+    return mask.astype(bool)

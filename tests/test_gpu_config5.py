@@ -88,6 +88,7 @@ def test_config5_fp32_all_pairs(setup):
 
 
 def _check_screened(st, mask, label):
+    mask = np.asarray(mask).astype(bool)
     spec, ref, e = st["spec"], st["ref"], st["e_pairs"]
     r = _build(st, mask)
     kept = np.triu(mask)
@@ -112,8 +113,12 @@ def _check_screened(st, mask, label):
 def test_config5_overlap_screen(setup):
     _say("config5 fp32 overlap screen rho_cut=%g" % RHO_CUT)
     st = setup
+    mask, rep = st["lib"].screen_mask(st["plan"], st["phi"], "overlap", rho_cut=RHO_CUT,
+                                      budget=TOL_EX_PER_ATOM * st["spec"].n_atoms)
+    # the library's decision equals the plain threshold on the integrals
     S = st["lib"].overlap_integrals(st["plan"], st["phi"]).cpu().numpy()
-    _check_screened(st, screening.overlap_mask(S, RHO_CUT), "overlap")
+    assert np.array_equal(mask.astype(bool), screening.overlap_mask(S, RHO_CUT))
+    _check_screened(st, mask, "overlap")
 
 
 def test_config5_mlp_screen(setup):
@@ -123,7 +128,8 @@ def test_config5_mlp_screen(setup):
     X, y = screening.training_data()
     params = screening.train_pair_mlp(X, y)
     wts = torch.from_numpy(screening.weights_to_array(params)).to("cuda:0")
-    _, feat = st["lib"].wannier(st["plan"], st["phi"])
-    pred = st["lib"].mlp_screen(st["plan"], feat, wts).cpu().numpy()
-    mask = screening.mask_by_budget(pred, TOL_EX_PER_ATOM * st["spec"].n_atoms)
+    mask, rep = st["lib"].screen_mask(st["plan"], st["phi"], "mlp",
+                                      budget=TOL_EX_PER_ATOM * st["spec"].n_atoms, weights=wts)
+    print("config5 mlp screen report:", rep, flush=True)
+    assert not rep["fallback"]
     _check_screened(st, mask, "mlp")

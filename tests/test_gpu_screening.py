@@ -95,22 +95,28 @@ def test_learned_screen_end_to_end(lib):
     # the three inputs leave about one decade of spread in log10 |e| at a given
     # distance (orbital orientation is not among them), so the fit is judged
     # by its mean error and the calibrated upper bound by its coverage
-    p_mean = screening.train_pair_mlp(X, y, epochs=60, upper_quantile=None)
+    p_mean = screening.train_pair_mlp(X, y, epochs=60, calibration=None)
     rmse = float(np.sqrt(np.mean((screening.forward(X, p_mean) - y) ** 2)))
-    p = screening.train_pair_mlp(X, y, epochs=60)
-    under = float(np.mean(screening.forward(X, p) < y))
-    print("training rmse (log10 |e|): %.3f, calibrated under-prediction %.3f, samples %d"
+    p_up = screening.train_pair_mlp(X, y, epochs=60, calibration="upper")
+    under = float(np.mean(screening.forward(X, p_up) < y))
+    print("training rmse (log10 |e|): %.3f, upper-bound under-prediction %.3f, samples %d"
           % (rmse, under, len(y)), flush=True)
     assert rmse < 1.3 and under < 0.07
+    # the screen itself uses the expected-value calibration
+    p = screening.train_pair_mlp(X, y, epochs=60)
     spec = synth.SystemSpec("held_out", 28.0, 64, 160, "water1", 40, (1.0, 2.0), 0.25, 77)
     s = synth.build_system(spec)
     _say("learned screen: held-out n=64 orbitals=160")
     plan = lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, "fp64", spec.alpha)
     phi = _dev(s.phi)
-    _, feat = lib.wannier(plan, phi)
-    pred = lib.mlp_screen(plan, feat, screening.weights_to_array(p)).cpu().numpy()
     budget = 1e-6 * spec.n_atoms
-    mask = screening.mask_by_budget(pred, budget)
+    wts = _dev(screening.weights_to_array(p))
+    mask, rep = lib.screen_mask(plan, phi, "mlp", budget=budget, weights=wts)
+    # the library's decision equals the plain rule on its own predictions
+    _, feat = lib.wannier(plan, phi)
+    pred = lib.mlp_screen(plan, feat, wts).cpu().numpy()
+    assert np.array_equal(mask, screening.mask_by_budget(pred, budget).astype(np.uint8))
+    assert not rep["fallback"] and rep["pairs_kept"] == int(mask.sum())
     full = lib.ace_build(plan, phi)
     scr = lib.ace_build(plan, phi, pair_mask=mask)
     torch.cuda.synchronize()
