@@ -339,6 +339,7 @@ def run_batch(args):
         plans.append(p)
     phis = [torch.from_numpy(s.phi).to(dev) for s in systems]
     batch = _lib.Batch(plans)
+    lanes, whole_tiles, other_tiles = batch.lanes()
     ws = _lib.workspace(batch.workspace_bytes(), dev)
     out = batch.outputs(phis)
     total_pairs = sum(sp.n_pairs for sp in specs)
@@ -400,6 +401,7 @@ def run_batch(args):
                                "%d pairs in all; step = one batch build"
                                % ([sp.n for sp in specs], [sp.n_orb for sp in specs], total_pairs),
                    "shapes": [list(p.tiling) for p in plans]},
+        "lanes": lanes, "tiles_in_shared_passes": whole_tiles, "tiles_other": other_tiles,
         "graph_ms": 1000 * t_graph, "eager_branches_ms": 1000 * t_eager,
         "sequential_ms": 1000 * t_seq, "speedup_vs_sequential": t_seq / t_graph,
         "ex_bitwise_equal_to_sequential": bool(np.array_equal(ex_graph, ex_seq)),

@@ -263,10 +263,17 @@ int ace_plan_set_schedule(ace_plan *plan, int schedule);
 /* ---- Batches of independent systems (uneven grids and orbital counts).
  *
  * One ace_build per instance (each with its own plan, launch shapes and
- * optional pair mask), recorded once into a HIP graph whose branches run
- * instances concurrently, largest first, balanced by estimated work; later
- * calls with the same pointers replay the recorded graph.  Every instance's
- * result is bitwise that of a separate ace_build with the same plan and mask.
+ * optional pair mask), recorded once into a HIP graph; later calls with the
+ * same pointers replay the recorded graph.  Instances with the same grid
+ * (48, 64, 80 or 96 points per axis), bulk precision and the automatic
+ * schedule form a lane: round r of a lane takes tile r of each of its
+ * instances, every whole three-pass tile of the round in one persistent
+ * launch per pass (workgroups draining a shared work queue of the
+ * instances' transform planes and point blocks), the lane's other tiles
+ * after them.  Lanes and the remaining instances run concurrently on the
+ * graph's branches, largest first, balanced by estimated work.  Every
+ * instance's result is bitwise that of a separate ace_build with the same
+ * plan and mask (the same arithmetic in the same order per instance).
  *
  * ace_batch_create: plans[count] (1 <= count <= ACE_BATCH_MAX) must outlive
  *   the batch and keep the launch shapes they had at creation (a changed
@@ -284,7 +291,10 @@ int ace_plan_set_schedule(ace_plan *plan, int schedule);
  *   records) the graph, launched on `stream`; ACE_BATCH_EAGER launches the
  *   same work directly on the branch streams, joined back into `stream`.
  *   A later call on another device returns ACE_ERR_ARG.
- * ace_batch_destroy: only after the batch's last build has completed. */
+ * ace_batch_destroy: only after the batch's last build has completed.
+ * ace_batch_lanes: host-side description of the schedule: *lanes lanes,
+ *   *batch_tiles tiles in the shared pass launches, *other_tiles tiles on
+ *   the single-system kernels (any pointer may be NULL). */
 #define ACE_BATCH_MAX 1024
 #define ACE_BATCH_EAGER 1
 typedef struct ace_batch ace_batch;
@@ -295,6 +305,8 @@ size_t ace_batch_workspace_bytes(const ace_batch *batch);
 int ace_batch_build(ace_batch *batch, void *stream, void *ws, size_t ws_bytes,
                     const double *const *phi, double *const *W, double *const *M,
                     double *const *xi, double *ex, int *info, int flags);
+int ace_batch_lanes(const ace_batch *batch, int *lanes, int64_t *batch_tiles,
+                    int64_t *other_tiles);
 
 /* ---- SCDM localisation (section "s-MTACE Method": a rank-revealing QR of
  * Psi^* selects columns of the density matrix Gamma = Psi Psi^*, which are

@@ -26,7 +26,7 @@ EXPORTS = ["ace_plan_create", "ace_plan_destroy", "ace_workspace_bytes",
            "ace_error_string", "ace_last_hip_error", "ace_set_profiling", "ace_profile_read",
            "ace_plan_set_tiling", "ace_plan_set_schedule", "ace_overlap_integrals", "ace_wannier", "ace_mlp_screen",
            "ace_mlp_weight_count", "ace_batch_create", "ace_batch_destroy",
-           "ace_batch_workspace_bytes", "ace_batch_build", "scdm_workspace_bytes",
+           "ace_batch_workspace_bytes", "ace_batch_build", "ace_batch_lanes", "scdm_workspace_bytes",
            "scdm_preselect", "scdm_localize", "ace_apply_noalloc", "ace_screen_mask",
            "ace_screen_mask_host"]
 PROBE_EXPORTS = ["ace_bandwidth_probe"]
@@ -120,6 +120,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ace_batch_build.argtypes = [vp, vp, vp, sz, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, i]
     lib.ace_batch_build.restype = i
+    lib.ace_batch_lanes.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int64)]
+    lib.ace_batch_lanes.restype = i
     lib.scdm_workspace_bytes.argtypes = [vp, i]
     lib.scdm_workspace_bytes.restype = sz
     lib.scdm_preselect.argtypes = [vp, vp, vp, sz, vp, vp, vp]
@@ -516,6 +519,14 @@ class Batch:
 
     def workspace_bytes(self) -> int:
         return int(load().ace_batch_workspace_bytes(self._h))
+
+    def lanes(self):
+        """(lanes, tiles in the shared pass launches, tiles on the single-system kernels)."""
+        n = ctypes.c_int()
+        bt, ot = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().ace_batch_lanes(self._h, ctypes.byref(n), ctypes.byref(bt), ctypes.byref(ot)),
+               "ace_batch_lanes")
+        return n.value, bt.value, ot.value
 
     def outputs(self, phis):
         """Fresh W, M, xi lists and ex[count], info[count] for phis."""

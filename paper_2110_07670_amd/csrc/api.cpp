@@ -76,6 +76,26 @@ struct BuildTables {
 };
 }  // namespace
 
+namespace {
+// Instances of a batch with one grid size, bulk precision and block whose full tiles
+// run in shared persistent pass launches.  Round r takes tile r of every
+// instance: the whole three-pass tiles as one launch per pass, the others
+// (partial, masked, chunked) with the single-system kernels after them.
+struct BatchLane {
+  int prec = 0, n = 0, block = 0, branch = 0;
+  double cost = 0.0;
+  std::vector<int> inst;  // instances, largest first
+  struct Round {
+    size_t seg0 = 0;        // pass q's segments: seg0 + q nseg ...
+    int nseg = 0;
+    int total[3] = {0, 0, 0};
+    int ctr = 0;            // pass q's queue counter: ctr + q
+    std::vector<std::pair<int, int>> rest;  // (position in inst, tile)
+  };
+  std::vector<Round> rounds;
+};
+}  // namespace
+
 struct ace_batch {
   int count = 0;
   std::vector<const ace_plan*> plans;
@@ -97,6 +117,17 @@ struct ace_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<const void*> key;       // pointers the recorded graph was made for
+  // the batch passes
+  std::vector<char> fused;            // instance belongs to a lane
+  std::vector<BatchLane> lanes;
+  std::vector<acex::BatchSeg> segs;   // sizes and counts; pointers filled per call
+  std::vector<std::pair<int, int>> seg_of;  // (instance, tile) of each segment
+  size_t off_seg = 0, off_ctr = 0;    // in the workspace, after the instances
+  int nctr = 0;
+  acex::BatchSeg* seg_pinned = nullptr;
+  hipEvent_t seg_ev = nullptr;        // the last upload of seg_pinned
+  bool seg_pending = false;
+  std::vector<const void*> seg_key;   // pointers seg_pinned holds
 };
 
 namespace {
@@ -447,16 +478,32 @@ int upload_tables(const ace_plan* p, hipStream_t s, char* w, const BuildTables& 
   return e == hipSuccess ? ACE_OK : hip_fail(e);
 }
 
-// A1-A10 on stream s, reading tables already resident in the workspace.
-int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
-                  const BuildTables& bt, double* W, double* M, double* xi, double* ex, int* info) {
-  hipError_t e;
-  const int B = p->block;
-  const Pack* d_packs = reinterpret_cast<const Pack*>(w + p->off_tab + bt.o_packs);
-  const int* d_meta = reinterpret_cast<const int*>(w + p->off_tab + bt.o_meta);
-  const int* d_orbs = reinterpret_cast<const int*>(w + p->off_tab + bt.o_orbs);
-
+// One build's launch context: the plan, its workspace and tables, the grid
+// arguments and the orbitals in the bulk precision.
+struct BuildCtx {
+  const ace_plan* p = nullptr;
+  char* w = nullptr;
+  const BuildTables* bt = nullptr;
   acex::GridArgs g;
+  const void* phi_bulk = nullptr;
+  const Pack* d_packs = nullptr;
+  const int* d_meta = nullptr;
+  const int* d_orbs = nullptr;
+  bool three_ok = false, rows_ok = false;
+};
+
+// Launch arguments and the W / FP32-copy prologue of a build on stream s,
+// reading tables already resident in the workspace.
+int build_begin(const ace_plan* p, hipStream_t s, char* w, const double* phi,
+                const BuildTables& bt, double* W, BuildCtx& c) {
+  hipError_t e;
+  c.p = p;
+  c.w = w;
+  c.bt = &bt;
+  c.d_packs = reinterpret_cast<const Pack*>(w + p->off_tab + bt.o_packs);
+  c.d_meta = reinterpret_cast<const int*>(w + p->off_tab + bt.o_meta);
+  c.d_orbs = reinterpret_cast<const int*>(w + p->off_tab + bt.o_orbs);
+  acex::GridArgs& g = c.g;
   g.n = p->n;
   g.prec = p->prec;
   g.npts = p->npts;
@@ -465,68 +512,83 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
   g.tw = w + p->off_tab + bt.o_tw;
   g.cus = device_cus();
   g.pencils = p->pencils;
-
-  const void* phi_bulk = phi;
-  {
-    ProfScope ps(p, 7, s);
-    if (p->prec == 1) {
-      e = acex::launch_cast_f64_f32(phi, reinterpret_cast<float*>(w + p->off_phi32),
-                                    (int64_t)p->n_orb * p->npts, s);
-      if (e != hipSuccess) return hip_fail(e);
-      phi_bulk = w + p->off_phi32;
-    }
-    e = acex::launch_fill_f64(W, 0.0, (int64_t)p->n_orb * p->npts, s);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-
-  // ---- A1-A5: pair densities, Poisson solves, W accumulation, tile by tile.
-  // Full tiles take three passes where the kernels fit (the inverse z
-  // transform feeds the W update directly); the others take four.
-  void* S = w + p->off_S;
   const bool fuse_ok = p->schedule == ACE_SCHEDULE_AUTO;
-  const bool three_ok = fuse_ok && acex::three_pass_ok(p->n, p->prec, B);
-  const bool rows_ok = fuse_ok && acex::fused_rows_ok(p->n, p->prec, B);
-  for (size_t ti = 0; ti < bt.tiles.size(); ++ti) {
-    const Tile& t = bt.tiles[ti];
-    // a full block x block tile with every pair kept (masked builds too)
-    const bool full = t.bi == B && t.bj == B && t.complete;
-    const bool three = three_ok && full;           // plane-fitting grids
-    const bool fused = (three_ok || rows_ok) && full;
-    const int* t_orbs = d_orbs + ti * (size_t)2 * B;
-    const int chunk = p->chunk > 0 ? p->chunk : t.npack;
-    for (int c0 = 0; c0 < t.npack; c0 += chunk) {
-      const int cnt = std::min(chunk, t.npack - c0);
-      void* Sc = static_cast<char*>(S) + (size_t)c0 * p->s_grid_bytes;
-      {
-        ProfScope ps(p, 0, s);
-        e = acex::launch_fwd_yz(g, phi_bulk, d_packs + t.pack0 + c0, cnt, Sc, s, three);
-        if (e != hipSuccess) return hip_fail(e);
-      }
-      {
-        ProfScope ps(p, 1, s);
-        e = three ? acex::launch_mid(g, Sc, cnt, s) : acex::launch_poisson_x(g, Sc, cnt, s);
-        if (e != hipSuccess) return hip_fail(e);
-      }
-      if (!three) {
-        ProfScope ps(p, 2, s);
-        e = fused ? acex::launch_inv_y(g, Sc, cnt, s) : acex::launch_inv_yz(g, Sc, cnt, s);
-        if (e != hipSuccess) return hip_fail(e);
-      }
+  c.three_ok = fuse_ok && acex::three_pass_ok(p->n, p->prec, p->block);
+  c.rows_ok = fuse_ok && acex::fused_rows_ok(p->n, p->prec, p->block);
+  c.phi_bulk = phi;
+  ProfScope ps(p, 7, s);
+  if (p->prec == 1) {
+    e = acex::launch_cast_f64_f32(phi, reinterpret_cast<float*>(w + p->off_phi32),
+                                  (int64_t)p->n_orb * p->npts, s);
+    if (e != hipSuccess) return hip_fail(e);
+    c.phi_bulk = w + p->off_phi32;
+  }
+  e = acex::launch_fill_f64(W, 0.0, (int64_t)p->n_orb * p->npts, s);
+  if (e != hipSuccess) return hip_fail(e);
+  return ACE_OK;
+}
+
+// Does the tile take the three-pass schedule as one launch per pass, with a
+// grid the batch kernels run?
+bool tile_batch_whole(const ace_plan* p, const Tile& t) {
+  const int B = p->block;
+  return p->schedule == ACE_SCHEDULE_AUTO && acex::batch_ok(p->n, p->prec, B) && t.bi == B &&
+         t.bj == B && t.complete && (p->chunk == 0 || p->chunk >= t.npack);
+}
+
+// A1-A5 for tile ti: pair densities, Poisson solves, W accumulation.  Full
+// tiles take three passes where the kernels fit (the inverse z transform
+// feeds the W update directly); the others take four.
+int build_tile(const BuildCtx& c, hipStream_t s, size_t ti, double* W) {
+  hipError_t e;
+  const ace_plan* p = c.p;
+  const acex::GridArgs& g = c.g;
+  const int B = p->block;
+  void* S = c.w + p->off_S;
+  const Tile& t = c.bt->tiles[ti];
+  // a full block x block tile with every pair kept (masked builds too)
+  const bool full = t.bi == B && t.bj == B && t.complete;
+  const bool three = c.three_ok && full;           // plane-fitting grids
+  const bool fused = (c.three_ok || c.rows_ok) && full;
+  const int* t_orbs = c.d_orbs + ti * (size_t)2 * B;
+  const int chunk = p->chunk > 0 ? p->chunk : t.npack;
+  for (int c0 = 0; c0 < t.npack; c0 += chunk) {
+    const int cnt = std::min(chunk, t.npack - c0);
+    void* Sc = static_cast<char*>(S) + (size_t)c0 * p->s_grid_bytes;
+    {
+      ProfScope ps(p, 0, s);
+      e = acex::launch_fwd_yz(g, c.phi_bulk, c.d_packs + t.pack0 + c0, cnt, Sc, s, three);
+      if (e != hipSuccess) return hip_fail(e);
     }
     {
-      ProfScope ps(p, 3, s);
-      if (fused) {
-        e = acex::launch_zinv_acc(g, B, t.diag, S, phi_bulk, W, t_orbs, p->alpha, s);
-      } else {
-        const bool full = t.bi == B && t.bj == B && t.complete;
-        e = acex::launch_accumulate(p->prec, B, t.diag, S, phi_bulk, W,
-                                    full ? nullptr : d_meta + t.pack0, t.npack, t_orbs, t.useI,
-                                    t.useJ, p->alpha, p->npts, s);
-      }
+      ProfScope ps(p, 1, s);
+      e = three ? acex::launch_mid(g, Sc, cnt, s) : acex::launch_poisson_x(g, Sc, cnt, s);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+    if (!three) {
+      ProfScope ps(p, 2, s);
+      e = fused ? acex::launch_inv_y(g, Sc, cnt, s) : acex::launch_inv_yz(g, Sc, cnt, s);
       if (e != hipSuccess) return hip_fail(e);
     }
   }
+  {
+    ProfScope ps(p, 3, s);
+    if (fused) {
+      e = acex::launch_zinv_acc(g, B, t.diag, S, c.phi_bulk, W, t_orbs, p->alpha, s);
+    } else {
+      e = acex::launch_accumulate(p->prec, B, t.diag, S, c.phi_bulk, W,
+                                  full ? nullptr : c.d_meta + t.pack0, t.npack, t_orbs, t.useI,
+                                  t.useJ, p->alpha, p->npts, s);
+    }
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return ACE_OK;
+}
 
+// A6-A10 once W is complete: M, the Cholesky factor and its inverse, xi, E_x.
+int build_end(const ace_plan* p, hipStream_t s, char* w, const double* phi, double* W, double* M,
+              double* xi, double* ex, int* info) {
+  hipError_t e;
   // ---- A6: M = dV Phi^T W
   double* part = reinterpret_cast<double*>(w + p->off_part);
   {
@@ -556,6 +618,19 @@ int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
     if (e != hipSuccess) return hip_fail(e);
   }
   return ACE_OK;
+}
+
+// A1-A10 on stream s, reading tables already resident in the workspace.
+int enqueue_build(const ace_plan* p, hipStream_t s, char* w, const double* phi,
+                  const BuildTables& bt, double* W, double* M, double* xi, double* ex, int* info) {
+  BuildCtx c;
+  int rc = build_begin(p, s, w, phi, bt, W, c);
+  if (rc != ACE_OK) return rc;
+  for (size_t ti = 0; ti < bt.tiles.size(); ++ti) {
+    rc = build_tile(c, s, ti, W);
+    if (rc != ACE_OK) return rc;
+  }
+  return build_end(p, s, w, phi, W, M, xi, ex, info);
 }
 
 }  // namespace
@@ -1008,14 +1083,105 @@ int ace_batch_create(ace_batch** batch, const ace_plan* const* plans,
   for (int k = 0; k < count; ++k) b->order[k] = k;
   std::stable_sort(b->order.begin(), b->order.end(),
                    [&](int x, int y) { return cost[x] > cost[y]; });
-  b->nbranch = std::min(count, kBatchBranches);
+  // lanes: instances with at least one whole three-pass tile, by (precision, grid, block)
+  b->fused.assign(count, 0);
+  std::vector<std::vector<char>> whole(count);
+  for (int k : b->order) {
+    const ace_plan* p = b->plans[k];
+    const std::vector<Tile>& tl = b->tables[k].tiles;
+    whole[k].assign(tl.size(), 0);
+    for (size_t ti = 0; ti < tl.size(); ++ti) {
+      whole[k][ti] = tile_batch_whole(p, tl[ti]) ? 1 : 0;
+      if (whole[k][ti]) b->fused[k] = 1;
+    }
+    if (!b->fused[k]) continue;
+    BatchLane* lane = nullptr;
+    for (BatchLane& l : b->lanes)
+      if (l.prec == p->prec && l.n == p->n && l.block == p->block) lane = &l;
+    if (!lane) {
+      b->lanes.emplace_back();
+      lane = &b->lanes.back();
+      lane->prec = p->prec;
+      lane->n = p->n;
+      lane->block = p->block;
+    }
+    lane->inst.push_back(k);
+    lane->cost += cost[k];
+  }
+  for (BatchLane& l : b->lanes) {
+    size_t R = 0;
+    for (int k : l.inst) R = std::max(R, b->tables[k].tiles.size());
+    l.rounds.resize(R);
+    for (size_t r = 0; r < R; ++r) {
+      BatchLane::Round& rd = l.rounds[r];
+      rd.seg0 = b->segs.size();
+      for (int q = 0; q < 3; ++q) {
+        int items = 0, nseg = 0;
+        for (size_t pos = 0; pos < l.inst.size(); ++pos) {
+          const int k = l.inst[pos];
+          const ace_plan* p = b->plans[k];
+          const std::vector<Tile>& tl = b->tables[k].tiles;
+          if (r >= tl.size()) continue;
+          if (!whole[k][r]) {
+            if (q == 0) rd.rest.emplace_back((int)pos, (int)r);
+            continue;
+          }
+          acex::BatchSeg sg{};
+          sg.npts = p->npts;
+          for (int a = 0; a < 3; ++a) sg.g2[a] = (kTwoPi / p->L[a]) * (kTwoPi / p->L[a]);
+          sg.kscale = 1.0 / (double)p->npts;
+          sg.alpha = p->alpha;
+          sg.n = p->n;
+          sg.npack = tl[r].npack;
+          sg.block = p->block;
+          sg.diag = tl[r].diag ? 1 : 0;
+          sg.item0 = items;
+          sg.count = acex::batch_items(q, p->n, tl[r].npack);
+          items += sg.count;
+          ++nseg;
+          b->segs.push_back(sg);
+          b->seg_of.emplace_back(k, (int)r);
+        }
+        rd.nseg = nseg;
+        rd.total[q] = items;
+      }
+      rd.ctr = b->nctr;
+      b->nctr += 3;
+    }
+  }
+  if (!b->segs.empty()) {
+    b->off_seg = off;
+    off += align256(b->segs.size() * sizeof(acex::BatchSeg));
+    b->off_ctr = off;
+    off += align256((size_t)b->nctr * sizeof(int));
+    b->total = off;
+  }
+  // branches: lanes and the other instances, largest first, each onto the
+  // branch with the least work so far
+  std::vector<std::pair<double, int>> units;  // (cost, lane l as -1 - l, or instance)
+  for (size_t l = 0; l < b->lanes.size(); ++l) units.emplace_back(b->lanes[l].cost, -1 - (int)l);
+  for (int k : b->order)
+    if (!b->fused[k]) units.emplace_back(cost[k], k);
+  std::stable_sort(units.begin(), units.end(),
+                   [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+                     return x.first > y.first;
+                   });
+  b->nbranch = std::min((int)units.size(), kBatchBranches);
   std::vector<double> load(b->nbranch, 0.0);
   b->branch.assign(count, 0);
-  for (int k : b->order) {
+  for (const auto& u : units) {
     const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    b->branch[k] = j;
-    load[j] += cost[k];
+    if (u.second < 0)
+      b->lanes[-1 - u.second].branch = j;
+    else
+      b->branch[u.second] = j;
+    load[j] += u.first;
   }
+  for (int k = 0; k < count; ++k)
+    if (b->fused[k])
+      for (const BatchLane& l : b->lanes)
+        for (int kk : l.inst)
+          if (kk == k) b->branch[k] = l.branch;
   *batch = b;
   return ACE_OK;
 }
@@ -1029,10 +1195,23 @@ void ace_batch_destroy(ace_batch* b) {
   if (b->fork) (void)hipEventDestroy(b->fork);
   for (hipEvent_t ev : b->join) (void)hipEventDestroy(ev);
   if (b->pinned) (void)hipHostFree(b->pinned);
+  if (b->seg_ev) (void)hipEventDestroy(b->seg_ev);
+  if (b->seg_pinned) (void)hipHostFree(b->seg_pinned);
   delete b;
 }
 
 size_t ace_batch_workspace_bytes(const ace_batch* b) { return b ? b->total : 0; }
+
+int ace_batch_lanes(const ace_batch* b, int* lanes, int64_t* batch_tiles, int64_t* other_tiles) {
+  if (!b) return ACE_ERR_ARG;
+  int64_t all = 0;
+  for (const BuildTables& bt : b->tables) all += (int64_t)bt.tiles.size();
+  const int64_t whole = (int64_t)b->seg_of.size() / 3;
+  if (lanes) *lanes = (int)b->lanes.size();
+  if (batch_tiles) *batch_tiles = whole;
+  if (other_tiles) *other_tiles = all - whole;
+  return ACE_OK;
+}
 
 int ace_batch_build(ace_batch* b, void* stream, void* ws, size_t ws_bytes,
                     const double* const* phi, double* const* W, double* const* M,
@@ -1075,6 +1254,13 @@ int ace_batch_build(ace_batch* b, void* stream, void* ws, size_t ws_bytes,
     if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
       return hip_fail(e);
+    if (!b->segs.empty()) {
+      e = hipHostMalloc(reinterpret_cast<void**>(&b->seg_pinned),
+                        b->segs.size() * sizeof(acex::BatchSeg), hipHostMallocDefault);
+      if (e != hipSuccess) return hip_fail(e);
+      if ((e = hipEventCreateWithFlags(&b->seg_ev, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e);
+    }
     for (int j = 0; j < b->nbranch; ++j) {
       hipStream_t st = nullptr;
       hipEvent_t ev = nullptr;
@@ -1098,18 +1284,95 @@ int ace_batch_build(ace_batch* b, void* stream, void* ws, size_t ws_bytes,
     if (e != hipSuccess) return hip_fail(e);
   }
 
-  // fork from `head` onto the branch streams, every instance on its branch, join back
+  // the batch-pass segments: device pointers of this call's arrays, written
+  // into the pinned copy only when they change (after its last upload has
+  // been read), uploaded in stream order like the tables
+  acex::BatchSeg* d_segs = reinterpret_cast<acex::BatchSeg*>(w + b->off_seg);
+  int* d_ctr = reinterpret_cast<int*>(w + b->off_ctr);
+  if (!b->segs.empty()) {
+    std::vector<const void*> sk;
+    sk.reserve(2 * b->count + 1);
+    sk.push_back(ws);
+    for (int k = 0; k < b->count; ++k) {
+      sk.push_back(phi[k]);
+      sk.push_back(W[k]);
+    }
+    if (sk != b->seg_key) {
+      if (b->seg_pending && (e = hipEventSynchronize(b->seg_ev)) != hipSuccess)
+        return hip_fail(e);
+      for (size_t i = 0; i < b->segs.size(); ++i) {
+        const int k = b->seg_of[i].first, ti = b->seg_of[i].second;
+        const ace_plan* p = b->plans[k];
+        const BuildTables& bt = b->tables[k];
+        char* pw = w + b->ws_off[k];
+        acex::BatchSeg sg = b->segs[i];
+        sg.phi = p->prec == 0 ? static_cast<const void*>(phi[k]) : pw + p->off_phi32;
+        sg.packs = reinterpret_cast<const Pack*>(pw + p->off_tab + bt.o_packs) + bt.tiles[ti].pack0;
+        sg.S = pw + p->off_S;
+        sg.tw = pw + p->off_tab + bt.o_tw;
+        sg.W = W[k];
+        sg.orbs = reinterpret_cast<const int*>(pw + p->off_tab + bt.o_orbs) + (size_t)ti * 2 * p->block;
+        b->seg_pinned[i] = sg;
+      }
+      b->seg_key = std::move(sk);
+    }
+    e = hipMemcpyAsync(d_segs, b->seg_pinned, b->segs.size() * sizeof(acex::BatchSeg),
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+    if ((e = hipEventRecord(b->seg_ev, s)) != hipSuccess) return hip_fail(e);
+    b->seg_pending = true;
+  }
+
+  // one lane on stream st: the instances' prologues, the rounds (batch passes,
+  // then the lane's other tiles of the round), the instances' dense tails
+  auto run_lane = [&](const BatchLane& l, hipStream_t st) -> int {
+    std::vector<BuildCtx> ctx(l.inst.size());
+    int rc = ACE_OK;
+    for (size_t pos = 0; pos < l.inst.size(); ++pos) {
+      const int k = l.inst[pos];
+      rc = build_begin(b->plans[k], st, w + b->ws_off[k], phi[k], b->tables[k], W[k], ctx[pos]);
+      if (rc != ACE_OK) return rc;
+    }
+    const int cus = device_cus();
+    for (const BatchLane::Round& rd : l.rounds) {
+      for (int q = 0; q < 3; ++q) {
+        const hipError_t er =
+            acex::launch_batch_pass(l.prec, q, l.n, l.block, d_segs + rd.seg0 + (size_t)q * rd.nseg, rd.nseg,
+                                    rd.total[q], d_ctr + rd.ctr + q, cus, st);
+        if (er != hipSuccess) return hip_fail(er);
+      }
+      for (const auto& pt : rd.rest) {
+        rc = build_tile(ctx[pt.first], st, (size_t)pt.second, W[l.inst[pt.first]]);
+        if (rc != ACE_OK) return rc;
+      }
+    }
+    for (size_t pos = 0; pos < l.inst.size(); ++pos) {
+      const int k = l.inst[pos];
+      rc = build_end(b->plans[k], st, w + b->ws_off[k], phi[k], W[k], M[k], xi[k], ex + k,
+                     info + k);
+      if (rc != ACE_OK) return rc;
+    }
+    return ACE_OK;
+  };
+
+  // fork from `head` onto the branch streams (lanes and the other instances
+  // on their branches), join back
   auto record = [&](hipStream_t head) -> int {
-    hipError_t er = hipEventRecord(b->fork, head);
-    if (er != hipSuccess) return hip_fail(er);
+    hipError_t er;
+    if (b->nctr > 0 && (er = acex::launch_fill_i32(d_ctr, 0, b->nctr, head)) != hipSuccess)
+      return hip_fail(er);
+    if ((er = hipEventRecord(b->fork, head)) != hipSuccess) return hip_fail(er);
     for (hipStream_t st : b->streams)
       if ((er = hipStreamWaitEvent(st, b->fork, 0)) != hipSuccess) return hip_fail(er);
     int rc = ACE_OK;
-    for (int k : b->order) {
-      const ace_plan* p = b->plans[k];
-      rc = enqueue_build(p, b->streams[b->branch[k]], w + b->ws_off[k], phi[k], b->tables[k],
-                         W[k], M[k], xi[k], ex + k, info + k);
+    for (const BatchLane& l : b->lanes) {
+      rc = run_lane(l, b->streams[l.branch]);
       if (rc != ACE_OK) break;
+    }
+    for (int k : b->order) {
+      if (rc != ACE_OK || b->fused[k]) continue;
+      rc = enqueue_build(b->plans[k], b->streams[b->branch[k]], w + b->ws_off[k], phi[k],
+                         b->tables[k], W[k], M[k], xi[k], ex + k, info + k);
     }
     // the join is recorded even after an error, so that a capture always closes
     for (int j = 0; j < b->nbranch; ++j) {

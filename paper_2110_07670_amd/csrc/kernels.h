@@ -76,6 +76,38 @@ hipError_t launch_accumulate(int prec, int block, bool diag, const void* S, cons
                              unsigned useI, unsigned useJ, double alpha, int64_t npts,
                              hipStream_t s);
 
+// ---- Batches: one persistent launch per pass over the three-pass tiles of
+// many systems of one grid size, bulk precision and block.  A launch drains a work
+// queue (an atomic counter) of items; segment k covers items item0 ..
+// item0 + count - 1 of one system's current tile: forward (pass 0) and
+// middle (pass 1) items are (x or kz, transform), N npack of them; fused
+// inverse-z/W items (pass 2) are the N N / 8 point blocks.  Each item does
+// the work of one workgroup of the single-system kernels, with the same
+// arithmetic, so results are bitwise those of the system's own build.
+struct BatchSeg {
+  const void* phi;      // orbitals in the bulk precision
+  const Pack* packs;    // the tile's transforms (pass 0)
+  void* S;              // the system's transform scratch
+  const void* tw;       // n twiddles, bulk precision
+  double* W;            // pass 2
+  const int* orbs;      // the tile's 2 block orbital indices (pass 2)
+  int64_t npts;
+  double g2[3];         // (2 pi / L_a)^2 (pass 1)
+  double kscale;        // 1 / N (pass 1)
+  double alpha;         // pass 2
+  int n, npack, block, diag;
+  int item0, count;
+};
+// Is a three-pass tile of this grid, bulk precision and block run by the
+// batch kernels?
+bool batch_ok(int n, int prec, int block);
+int batch_items(int pass, int n, int npack);
+// One launch of pass `pass` over the segments of one grid size n, bulk
+// precision and block; counter must read 0 when the launch starts.
+hipError_t launch_batch_pass(int prec, int pass, int n, int block, const BatchSeg* segs, int nseg,
+                             int total, int* counter, int cus, hipStream_t s);
+hipError_t launch_fill_i32(int* p, int v, int64_t count, hipStream_t s);
+
 // Pair energies from the per-workgroup partial sums.
 // e_pack[p] = sum of the parts of pack p (fixed order) * omega / N^2.
 hipError_t launch_energy_reduce(const double* part, int npack, int parts, double factor,

@@ -16,6 +16,9 @@
 // position a + N2*b holds frequency b + N1*a; the inverse consumes it, so no
 // reordering pass exists anywhere.  Where a plane does not fit the 160 KiB
 // LDS, the y/z stage is split into a row (z) pass and a column (y) pass.
+#include <algorithm>
+#include <atomic>
+
 #include "fft_core.h"
 #include "kernels.h"
 
@@ -110,6 +113,18 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// The thread index as a value the compiler cannot see through: in the
+// persistent batch loops this keeps the per-thread index arithmetic of an
+// item inside the item instead of hoisted out of the loop and held in
+// registers across all of them (which cost the loops their occupancy).
+template <int NT>
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  __asm__ volatile("" : "+v"(t));
+  __builtin_assume(t >= 0 && t < NT);
+  return t;
+}
+
 template <typename T, int N>
 __device__ __forceinline__ T coulomb_k(int kx, int ky, int kz, T g0, T g1, T g2, T kscale) {
   const int mx = kx <= N / 2 ? kx : kx - N;
@@ -140,20 +155,23 @@ __device__ __forceinline__ void plane_item(int item, int npack, int& x, int& p) 
 
 // ZXY: write the result as S[kz][x][ky] (the three-pass schedule, whose middle
 // pass reads one kz plane contiguously) instead of S[x][ky][kz].
-template <typename T, int N, bool ZXY>
-__global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
-    const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
-    cx<T>* __restrict__ S, int npack, int64_t npts) {
+// The loop of one forward-plane workgroup of NT threads over the items that
+// the source Q hands it: Q::first() (called by every thread), Q::ask() at the
+// top of an item and Q::post() before its first barrier (a queue fetches
+// the next item there), Q::next(item) after that barrier, Q::more(item), and
+// Q::at(item, phi, pack, out, x): the orbitals, the pack, the transform's
+// scratch grid and the plane x of an item.  lds holds N (N + 1) values,
+// stw N.
+template <typename T, int N, bool ZXY, int NT, class Q>
+__device__ __forceinline__ void plane_fwd_loop(Q& q, const cx<T>* __restrict__ tw, int64_t npts,
+                                               cx<T>* __restrict__ lds, cx<T>* __restrict__ stw) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
-  constexpr int NT = fwd_threads<N>();
   constexpr int Q1 = (N * N2 + NT - 1) / NT;  // z-step-1 tasks per thread
   static_assert(NT % N2 == 0, "threads must be a multiple of N2");
-  __shared__ cx<T> lds[N * P];
-  __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
   const int t2 = tid % N2;
-  const int nitems = N * npack;
   for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];  // stw[k1 N2 + t2] = w^(t2 k1)
+  int item = q.first();
   __syncthreads();
 
   // row of z-step-1 task group g: with eight lanes per row, the two halves of
@@ -168,9 +186,11 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
   // phi_a, phi_b, phi_d of one item at this thread's z-step-1 elements
   T fa[Q1][N1], fb[Q1][N1], fd[Q1][N1];
   auto fetch = [&](int it) __attribute__((always_inline)) {
-    int x, p;
-    plane_item<T, N>(it, npack, x, p);
-    const Pack pk = packs[p];
+    const T* phi;
+    Pack pk;
+    cx<T>* o;
+    int x;
+    q.at(it, phi, pk, o, x);
     const int64_t plane = (int64_t)x * N * N;
     const T* __restrict__ pa = phi + (int64_t)pk.a * npts + plane;
     const T* __restrict__ pb = phi + (int64_t)pk.b * npts + plane;
@@ -189,12 +209,15 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
     }
   };
 
-  int item = blockIdx.x;
-  if (item < nitems) fetch(item);
-  while (item < nitems) {
-    int x, p;
-    plane_item<T, N>(item, npack, x, p);
-    const T dmask = packs[p].c >= 0 ? T(1) : T(0);
+  if (q.more(item)) fetch(item);
+  while (q.more(item)) {
+    const T* phi_unused;
+    Pack pk;
+    cx<T>* S;
+    int x;
+    q.at(item, phi_unused, pk, S, x);
+    q.ask();
+    const T dmask = pk.c >= 0 ? T(1) : T(0);
     const int64_t plane = (int64_t)x * N * N;
     // z step 1: tasks (y, t2), t2 fastest (coalesced along z)
 #pragma unroll
@@ -213,7 +236,9 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
         for (int k1 = 0; k1 < N1; ++k1) lds[y * P + t2 + N2 * k1] = v[k1];
       }
     }
+    q.post();
     lds_barrier();
+    const int next = q.next(item);
     // z step 2: tasks (y, k1), y fastest
 #pragma unroll 1
     for (int task = tid; task < N * N1; task += NT) {
@@ -239,14 +264,13 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
 #pragma unroll
       for (int k1 = 0; k1 < N1; ++k1) lds[(u2 + N2 * k1) * P + pz] = v[k1];
     }
-    const int next = item + gridDim.x;
     __builtin_amdgcn_sched_barrier(0);  // keep the prefetch below the y-step-1 work
-    if (next < nitems) fetch(next);
+    if (q.more(next)) fetch(next);
     __builtin_amdgcn_sched_barrier(0);
     lds_barrier();
     if constexpr (!ZXY) {
       // y step 2 -> global: tasks (pz, k1), pz fastest (coalesced)
-      cx<T>* __restrict__ out = S + (int64_t)p * npts + plane;
+      cx<T>* __restrict__ out = S + plane;
 #pragma unroll 1
       for (int task = tid; task < N * N1; task += NT) {
         const int pz = task % N, k1 = task / N;
@@ -273,7 +297,7 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
         for (int t = 0; t < N2; ++t) lds[(t + N2 * k1) * P + pz] = v[t];
       }
       lds_barrier();
-      cx<T>* __restrict__ out = S + (int64_t)p * npts + (int64_t)x * N;
+      cx<T>* __restrict__ out = S + (int64_t)x * N;
 #pragma unroll 1
       for (int e = tid; e < N * N; e += NT) {
         const int ky = e % N, pz = e / N;
@@ -283,6 +307,38 @@ __global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
     lds_barrier();
     item = next;
   }
+}
+
+// Items of one tile: (x, pack) in plane_item order, strided by the grid.
+template <typename T, int N>
+struct FwdTile {
+  const T* phi;
+  const Pack* packs;
+  cx<T>* S;
+  int npack;
+  int64_t npts;
+  __device__ __forceinline__ int first() const { return blockIdx.x; }
+  __device__ __forceinline__ void ask() {}
+  __device__ __forceinline__ void post() {}
+  __device__ __forceinline__ int next(int it) const { return it + gridDim.x; }
+  __device__ __forceinline__ bool more(int it) const { return it < N * npack; }
+  __device__ __forceinline__ void at(int it, const T*& f, Pack& pk, cx<T>*& o, int& x) const {
+    int p;
+    plane_item<T, N>(it, npack, x, p);
+    f = phi;
+    pk = packs[p];
+    o = S + (int64_t)p * npts;
+  }
+};
+
+template <typename T, int N, bool ZXY>
+__global__ __launch_bounds__(fwd_threads<N>()) void k_plane_fwd(
+    const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
+    cx<T>* __restrict__ S, int npack, int64_t npts) {
+  __shared__ cx<T> lds[N * (N + 1)];
+  __shared__ cx<T> stw[N];
+  FwdTile<T, N> q{phi, packs, S, npack, npts};
+  plane_fwd_loop<T, N, ZXY, fwd_threads<N>()>(q, tw, npts, lds, stw);
 }
 
 // ------------------------------------------------------------------ y/z plane, inverse
@@ -368,17 +424,15 @@ constexpr int row_pack0(int a) {
 //   k_zinv_acc       : inverse z of a tile's transforms at the points
 //                      (x, y0..y0+7, all z), folded straight into W.
 // The potentials never make a round trip through HBM in real space.
-template <typename T, int N>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
-    cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts, T g0, T g1,
-    T g2, T kscale) {
+// The work of one middle-pass workgroup of NT threads: item bid = (kz
+// position, transform); lds holds N (N + 1) values, stw N.
+template <typename T, int N, int NT, bool LOOP = false>
+__device__ __forceinline__ void plane_mid_item(cx<T>* __restrict__ S, const cx<T>* __restrict__ tw,
+                                               int64_t npts, T g0, T g1, T g2, T kscale, int bid,
+                                               cx<T>* __restrict__ lds, cx<T>* __restrict__ stw) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
-  constexpr int NT = plane_threads<N>();
-  __shared__ cx<T> lds[N * P];
-  __shared__ cx<T> stw[N];
-  const int bid = blockIdx.x;
   const int pz = bid % N, p = bid / N;
-  const int tid = threadIdx.x;
+  const int tid = LOOP ? opaque_tid<NT>() : (int)threadIdx.x;
   for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];  // stw[k1 N2 + t2] = w^(t2 k1)
   cx<T>* __restrict__ io = S + (int64_t)p * npts + (int64_t)pz * N * N;
   const int kz = freq_of_pos<N>(pz);
@@ -450,6 +504,15 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
   }
 }
 
+template <typename T, int N>
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
+    cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts, T g0, T g1,
+    T g2, T kscale) {
+  __shared__ cx<T> lds[N * (N + 1)];
+  __shared__ cx<T> stw[N];
+  plane_mid_item<T, N, plane_threads<N>()>(S, tw, npts, g0, g1, g2, kscale, blockIdx.x, lds, stw);
+}
+
 // Rows of y per inverse-z workgroup (one workgroup: rows x N points).  Eight
 // rows read 128 B (FP64) of each scratch row per transform; four FP64 rows
 // (64 B segments, two workgroups per CU) measured slower, even with the two
@@ -475,21 +538,26 @@ constexpr bool zinv_ok() {
 // them into the W sums it keeps in registers.  Off-diagonal tiles: W_a is
 // updated once per row (sum_b v_ab phi_b) and the B sums of W_J at the end;
 // diagonal tiles: all B sums at the end.  Fixed order, no atomics.
-template <typename T, int N, int B, bool DIAG, bool ROWS>
-__global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
-    const cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, const T* __restrict__ phi,
-    double* __restrict__ W, const int* __restrict__ orbs, double alpha, int64_t npts) {
+// The work of one such workgroup of NT >= YC N threads (threads past YC N
+// take part in the transforms and barriers but own no point): item bid =
+// (x, y0); lds holds B / 2 YC (N + 1) values, stw N.
+template <typename T, int N, int B, bool DIAG, bool ROWS, int NT, bool LOOP = false>
+__device__ __forceinline__ void zinv_item(const cx<T>* __restrict__ S,
+                                          const cx<T>* __restrict__ tw, const T* __restrict__ phi,
+                                          double* __restrict__ W, const int* __restrict__ orbs,
+                                          double alpha, int64_t npts, int bid,
+                                          cx<T>* __restrict__ lds, cx<T>* __restrict__ stw) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
-  constexpr int NT = zinv_threads<T, N, ROWS>(), G = B / 2, YC = zinv_rows<T, ROWS>();
+  constexpr int G = B / 2, YC = zinv_rows<T, ROWS>();
+  constexpr int ACT = zinv_threads<T, N, ROWS>();  // threads that own a point
+  static_assert(NT >= ACT, "a thread per point");
   // kz positions and rows in the scratch: S[kz][x][y] (kz stride N^2, rows
   // adjacent) or, with ROWS, S[x][y][kz] (kz adjacent, rows N apart)
   constexpr int64_t KS = ROWS ? 1 : (int64_t)N * N;
   constexpr int64_t CS = ROWS ? N : 1;
   static_assert(B % 2 == 0, "rows of a full tile pack evenly");
-  __shared__ cx<T> lds[G * YC * P];
-  __shared__ cx<T> stw[N];
-  const int tid = threadIdx.x;
-  const int bid = blockIdx.x;
+  const int tid = LOOP ? opaque_tid<NT>() : (int)threadIdx.x;
+  const bool act = NT == ACT || tid < ACT;
   int x, y0;
   // workgroups per 128-byte scratch segment (FP32: two)
   constexpr int H = YC * int(sizeof(cx<T>)) < 128 ? 128 / (YC * int(sizeof(cx<T>))) : 1;
@@ -506,8 +574,9 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
     x = bid / (N / YC);
   }
   for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];  // stw[k1 N2 + t2] = w^(t2 k1)
-  // this thread's point for the W update (consecutive threads: consecutive z)
-  const int c = tid / N, z = tid % N;
+  // this thread's point for the W update (consecutive threads: consecutive
+  // z); a thread without one reads point (x, y0, z) and writes nothing
+  const int c = act ? tid / N : 0, z = tid % N;
   const int64_t r = ((int64_t)x * N + y0 + c) * N + z;
   const cx<T>* __restrict__ sx =
       S + (ROWS ? ((int64_t)x * N + y0) * N : (int64_t)x * N + y0);  // + pack npts + c CS + pz KS
@@ -646,7 +715,7 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
         acc[2 * m] += v0 * phA;
         acc[2 * m + 1] += v1 * phA;
       }
-      __builtin_nontemporal_store(wA - alpha * accA, &W[oa]);
+      if (act) __builtin_nontemporal_store(wA - alpha * accA, &W[oa]);
     } else {
       // row a at compile time, so every register index is static
       sfor<0, B>([&](auto ac) {
@@ -677,10 +746,22 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
 #pragma unroll
   for (int b = 0; b < B; ++b)
     wold[b] = __builtin_nontemporal_load(&W[(int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r]);
+  if (act) {
 #pragma unroll
-  for (int b = 0; b < B; ++b)
-    __builtin_nontemporal_store(wold[b] - alpha * acc[b],
-                                &W[(int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r]);
+    for (int b = 0; b < B; ++b)
+      __builtin_nontemporal_store(wold[b] - alpha * acc[b],
+                                  &W[(int64_t)orbs[(DIAG ? 0 : B) + b] * npts + r]);
+  }
+}
+
+template <typename T, int N, int B, bool DIAG, bool ROWS>
+__global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
+    const cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, const T* __restrict__ phi,
+    double* __restrict__ W, const int* __restrict__ orbs, double alpha, int64_t npts) {
+  __shared__ cx<T> lds[(B / 2) * zinv_rows<T, ROWS>() * (N + 1)];
+  __shared__ cx<T> stw[N];
+  zinv_item<T, N, B, DIAG, ROWS, zinv_threads<T, N, ROWS>()>(S, tw, phi, W, orbs, alpha, npts,
+                                                               blockIdx.x, lds, stw);
 }
 
 // ------------------------------------------------------------------ z rows (fallback)
@@ -1074,6 +1155,198 @@ __global__ void k_cast_f64_f32(const double* __restrict__ in, float* __restrict_
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = i; k < count; k += stride) out[k] = float(in[k]);
+}
+
+// ------------------------------------------------------------------ batches
+// Persistent pass kernels over the whole three-pass tiles of many systems of
+// one grid size and bulk precision (a lane round: segment k of the table
+// covers items item0 .. item0 + count - 1 of one system's tile).  Forward
+// items all cost the same, so each workgroup takes every grid-th item of the
+// round, which lets it load the next item's orbitals during the current
+// one, as the single-system kernel does; middle and inverse-z/W items are
+// taken from a work queue (one atomic counter per launch) until it is empty.
+// Each item runs the single-system code for its block and diagonal flag.
+// One kernel per grid size (48, 64, 80, 96: a plane fits one workgroup's
+// LDS in FP64 and FP32), with that size's 8 N threads: one kernel over all
+// sizes took the register allocation of the largest into every path, and a
+// common thread count idled threads on the smaller grids.
+#define ACEX_BATCH_SIZES(X) X(48) X(64) X(80) X(96)
+
+template <int N>
+constexpr int batch_threads() { return 8 * N; }
+
+// the last segment that starts at or before item (uniform across the workgroup)
+__device__ __forceinline__ int batch_seg(const BatchSeg* __restrict__ segs, int nseg, int item) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].item0 <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Forward items of a lane round, strided by the grid.
+template <typename T, int N>
+struct FwdLane {
+  const BatchSeg* segs;
+  int nseg, total;
+  int64_t npts;
+  __device__ __forceinline__ int first() const { return blockIdx.x; }
+  __device__ __forceinline__ void ask() {}
+  __device__ __forceinline__ void post() {}
+  __device__ __forceinline__ int next(int it) const { return it + gridDim.x; }
+  __device__ __forceinline__ bool more(int it) const { return it < total; }
+  __device__ __forceinline__ void at(int it, const T*& f, Pack& pk, cx<T>*& o, int& x) const {
+    const BatchSeg& g = segs[batch_seg(segs, nseg, it)];
+    int p;
+    plane_item<T, N>(it - g.item0, g.npack, x, p);
+    f = static_cast<const T*>(g.phi);
+    pk = g.packs[p];
+    o = static_cast<cx<T>*>(g.S) + (int64_t)p * npts;
+  }
+};
+
+// Middle (PASS 1) and inverse-z/W (PASS 2, block B) items.
+template <typename T, int PASS, int N, int B>
+__device__ __forceinline__ void batch_item(const BatchSeg& g, int local, cx<T>* __restrict__ smem) {
+  constexpr int NT = batch_threads<N>();
+  if constexpr (PASS == 1) {
+    plane_mid_item<T, N, NT, true>(static_cast<cx<T>*>(g.S), static_cast<const cx<T>*>(g.tw),
+                                   g.npts, T(g.g2[0]), T(g.g2[1]), T(g.g2[2]), T(g.kscale), local,
+                                   smem, smem + N * (N + 1));
+  } else {
+    cx<T>* stw = smem + (B / 2) * zinv_rows<T>() * (N + 1);
+    const cx<T>* S = static_cast<const cx<T>*>(g.S);
+    const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
+    const T* phi = static_cast<const T*>(g.phi);
+    if (g.diag)
+      zinv_item<T, N, B, true, false, NT, true>(S, tw, phi, g.W, g.orbs, g.alpha, g.npts, local,
+                                                smem, stw);
+    else
+      zinv_item<T, N, B, false, false, NT, true>(S, tw, phi, g.W, g.orbs, g.alpha, g.npts, local,
+                                                 smem, stw);
+  }
+}
+
+// Waves per SIMD each batch kernel is compiled for: the workgroups per CU of
+// the single-system kernel of the same pass and grid (their registers and
+// LDS), where the persistent loop would otherwise take more registers and
+// fit fewer (1: no bound beyond the workgroup size).
+template <typename T, int PASS, int N, int B>
+constexpr int batch_waves() {
+  constexpr bool F = sizeof(T) == 4;
+  if (PASS == 1) {
+    if (N == 48) return F ? 1 : 6;
+    if (N == 64 || N == 80) return F ? 8 : 1;
+    return F ? 6 : 1;
+  }
+  return 1;
+}
+
+// PASS 0 and 1 take B = 0; PASS 2 one kernel per block.
+template <typename T, int PASS, int N, int B>
+__global__ __launch_bounds__(batch_threads<N>())
+__attribute__((amdgpu_waves_per_eu(batch_waves<T, PASS, N, B>()))) void k_batch_pass(
+    const BatchSeg* __restrict__ segs, int nseg, int total, int* __restrict__ counter) {
+  __shared__ cx<T> smem[PASS == 2 ? (B / 2) * zinv_rows<T>() * (N + 1) + N : N * (N + 1) + N];
+  if constexpr (PASS == 0) {
+    FwdLane<T, N> q{segs, nseg, total, (int64_t)N * N * N};
+    plane_fwd_loop<T, N, true, batch_threads<N>()>(q, static_cast<const cx<T>*>(segs[0].tw),
+                                                   (int64_t)N * N * N, smem, smem + N * (N + 1));
+  } else {
+    __shared__ int s_item;
+    for (;;) {
+      if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+      __syncthreads();
+      const int item = __builtin_amdgcn_readfirstlane(s_item);
+      // every thread has its item (and has left the previous one) before
+      // thread 0 takes the next or anyone reuses the LDS
+      __syncthreads();
+      if (item >= total) break;  // the same for the whole workgroup
+      const int k = batch_seg(segs, nseg, item);
+      batch_item<T, PASS, N, B>(segs[k], item - segs[k].item0, smem);
+    }
+  }
+}
+
+bool batch_ok(int n, int prec, int block) {
+  if (block != 8 && block != 16) return false;
+  switch (n) {
+#define X(NN) case NN:
+    ACEX_BATCH_SIZES(X)
+#undef X
+    break;
+    default: return false;
+  }
+  return three_pass_ok(n, prec, block);
+}
+
+int batch_items(int pass, int n, int npack) {
+  return pass == 2 ? n * (n / zinv_rows<double>()) : n * npack;
+}
+
+// Workgroups of a batch pass resident per CU (LDS and registers), looked up
+// once per kernel.
+template <typename T, int PASS, int N, int B>
+static int batch_per_cu() {
+  static std::atomic<int> cached{0};
+  const int v = cached.load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_pass<T, PASS, N, B>,
+                                                   batch_threads<N>(), 0) != hipSuccess ||
+      occ < 1)
+    occ = 1;
+  cached.store(occ, std::memory_order_relaxed);
+  return occ;
+}
+
+template <typename T, int PASS, int N, int B>
+static hipError_t batch_launch(const BatchSeg* segs, int nseg, int total, int* counter, int cus,
+                               hipStream_t s) {
+  static_assert(zinv_threads<T, N>() <= batch_threads<N>(), "a thread per inverse-z point");
+  static_assert(plane_ok<T, N>(), "a plane per workgroup");
+  const int grid = std::min(total, cus * batch_per_cu<T, PASS, N, B>());
+  hipLaunchKernelGGL((k_batch_pass<T, PASS, N, B>), dim3(grid), dim3(batch_threads<N>()), 0, s,
+                     segs, nseg, total, counter);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t batch_t(int pass, int block, const BatchSeg* segs, int nseg, int total,
+                          int* counter, int cus, hipStream_t s) {
+  if (pass == 0) return batch_launch<T, 0, N, 0>(segs, nseg, total, counter, cus, s);
+  if (pass == 1) return batch_launch<T, 1, N, 0>(segs, nseg, total, counter, cus, s);
+  if (pass == 2 && block == 16) return batch_launch<T, 2, N, 16>(segs, nseg, total, counter, cus, s);
+  if (pass == 2 && block == 8) return batch_launch<T, 2, N, 8>(segs, nseg, total, counter, cus, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_pass(int prec, int pass, int n, int block, const BatchSeg* segs, int nseg,
+                             int total, int* counter, int cus, hipStream_t s) {
+  if (nseg <= 0 || total <= 0) return hipSuccess;
+  switch (n) {
+#define X(NN)                                                                               \
+  case NN:                                                                                  \
+    return prec == 0 ? batch_t<double, NN>(pass, block, segs, nseg, total, counter, cus, s) \
+                     : batch_t<float, NN>(pass, block, segs, nseg, total, counter, cus, s);
+    ACEX_BATCH_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+__global__ void k_fill_i32(int* __restrict__ p, int v, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int* p, int v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v,
+                     count);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ dispatch

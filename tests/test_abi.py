@@ -178,6 +178,11 @@ def test_batch_create_and_workspace():
     total = lib.ace_batch_workspace_bytes(b)
     each = [lib.ace_workspace_bytes(h) for h in hs]
     assert total == sum((x + 255) // 256 * 256 for x in each)
+    # no grid of a shared pass kernel: no lane, every tile on its own kernels
+    n, bt, ot = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
+    assert lib.ace_batch_lanes(b, ctypes.byref(n), ctypes.byref(bt), ctypes.byref(ot)) == 0
+    assert (n.value, bt.value, ot.value) == (0, 0, 1 + 1 + 1)
+    assert lib.ace_batch_lanes(None, None, None, None) == _lib.ACE_ERR_ARG
     lib.ace_batch_destroy(b)
     # a null plan is rejected
     arr2 = (ctypes.c_void_p * 2)(hs[0], None)
@@ -186,6 +191,31 @@ def test_batch_create_and_workspace():
     m = np.ones((6, 6), dtype=np.uint8)
     masks = (ctypes.c_void_p * 3)(None, m.ctypes.data, None)
     assert lib.ace_batch_create(ctypes.byref(b), arr, masks, 3) == 0
+    lib.ace_batch_destroy(b)
+    for h in hs:
+        lib.ace_plan_destroy(h)
+
+
+def test_batch_lanes_group_grids_and_precisions():
+    """Instances of one grid and bulk precision share a lane; its whole
+    three-pass tiles go to the shared pass launches, a lane round per tile
+    index, the partial tiles to the single-system kernels; the segments and
+    queue counters extend the workspace past the instances'."""
+    lib = _lib.load()
+    # 48^3 with 20 orbitals (block 16: one whole diagonal tile, two partial),
+    # 48^3 with 16 orbitals (one whole tile), 64^3 with 8 (one partial tile)
+    hs = []
+    for n, k in [(48, 20), (48, 16), (64, 8)]:
+        rc, h = _create(_desc(n=n, k=k))
+        assert rc == 0
+        hs.append(h)
+    b = ctypes.c_void_p()
+    assert lib.ace_batch_create(ctypes.byref(b), (ctypes.c_void_p * 3)(*hs), None, 3) == 0
+    n, bt, ot = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
+    assert lib.ace_batch_lanes(b, ctypes.byref(n), ctypes.byref(bt), ctypes.byref(ot)) == 0
+    assert (n.value, bt.value, ot.value) == (1, 2, 2 + 1)
+    each = sum((lib.ace_workspace_bytes(h) + 255) // 256 * 256 for h in hs)
+    assert lib.ace_batch_workspace_bytes(b) > each
     lib.ace_batch_destroy(b)
     for h in hs:
         lib.ace_plan_destroy(h)

@@ -17,13 +17,23 @@ from paper_2110_07670_amd import synth
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
-# (n, orbitals, precision, (block, chunk, pencils), masked)
+# (n, orbitals, precision, (block, chunk, pencils), mask: None, "random" or
+# "tail" (pairs of the first 16 orbitals all kept, the rest random))
+# The last five take the persistent batch passes for their whole tiles: a
+# lane of two instances with unequal tile counts (48 FP32), one instance with
+# a mask whose leading tiles are complete, and the partial tiles of all of
+# them between the passes.
 INSTANCES = [
-    (16, 4, "fp64", (16, 0, 0), False),
-    (24, 13, "fp64", (8, 0, 8), False),
-    (32, 9, "fp64", (16, 5, 32), True),
-    (40, 6, "fp32", (16, 0, 0), False),
-    (48, 20, "fp64", (8, 7, 16), False),
+    (16, 4, "fp64", (16, 0, 0), None),
+    (24, 13, "fp64", (8, 0, 8), None),
+    (32, 9, "fp64", (16, 5, 32), "random"),
+    (40, 6, "fp32", (16, 0, 0), None),
+    (48, 20, "fp64", (8, 7, 16), None),
+    (48, 20, "fp32", (8, 0, 0), None),
+    (64, 17, "fp64", (16, 0, 0), None),
+    (48, 9, "fp32", (8, 0, 0), None),
+    (64, 22, "fp64", (8, 0, 0), "tail"),
+    (80, 8, "fp32", (8, 0, 16), None),
 ]
 
 
@@ -50,9 +60,11 @@ def _host(t):
     return t.detach().cpu().numpy()
 
 
-def _mask(k, seed):
+def _mask(k, seed, kind="random"):
     rng = np.random.default_rng(seed)
     m = rng.random((k, k)) < 0.6
+    if kind == "tail":
+        m[:16, :16] = True
     m = m | m.T
     np.fill_diagonal(m, True)
     return m.astype(np.uint8)
@@ -65,7 +77,7 @@ def systems():
         L = 0.11 * n + 5.0
         spec = synth.SystemSpec("b%d" % idx, L, n, k, "random", 0, (1.0, 1.4), 0.25, 70 + idx)
         s = synth.build_system(spec)
-        out.append((spec, s, prec, shape, _mask(k, 90 + idx) if masked else None))
+        out.append((spec, s, prec, shape, _mask(k, 90 + idx, masked) if masked else None))
     return out
 
 
@@ -99,11 +111,15 @@ def _assert_same(out, refs):
 
 def test_batch_graph_matches_separate_builds_and_replays(lib, systems):
     import torch
-    _say("batch graph: 5 uneven instances n=16..48")
+    _say("batch graph: %d uneven instances n=16..80" % len(systems))
     plans = _plans(lib, systems)
     phis = [_dev(s.phi) for _, s, _, _, _ in systems]
     refs = _separate(lib, plans, systems, phis)
     batch = lib.Batch(plans, [m for *_, m in systems])
+    # lanes: 48^3 FP32 block 8 (two instances), 64^3 FP64 block 16 and
+    # block 8 (one each), 80^3 FP32 block 8 (one)
+    lanes, whole, other = batch.lanes()
+    assert lanes == 4 and whole > 0 and other > 0
     ws = lib.workspace(batch.workspace_bytes())
     out = batch.outputs(phis)
     batch.build_into(phis, out, ws)
