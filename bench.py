@@ -331,12 +331,13 @@ def run_batch(args):
         say("built %s n=%d orbitals=%d" % (sp.name, sp.n, sp.n_orb))
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
-    plans = []
-    for sp in specs:
-        p = _lib.Plan(sp.n, (sp.L,) * 3, sp.n_orb, args.precision, sp.alpha)
-        if not args.no_tune:
-            autotune.apply(p, args.precision, cache_path=args.tune_cache, log=say)
-        plans.append(p)
+    plans = [_lib.Plan(sp.n, (sp.L,) * 3, sp.n_orb, args.precision, sp.alpha) for sp in specs]
+    tuned = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tuned = autotune.tune_batch(plans, args.precision, cache_path=args.tune_cache, log=say)
+        tuned = {"batch_ms": tuned["ms"], "trials": [t[0] for t in tuned["tried"]],
+                 "tune_s": round(time.perf_counter() - t0, 1)}
     phis = [torch.from_numpy(s.phi).to(dev) for s in systems]
     batch = _lib.Batch(plans)
     lanes, whole_tiles, other_tiles = batch.lanes()
@@ -390,6 +391,10 @@ def run_batch(args):
               for s, v in agg.items()}
     dom = max(mem_stages, key=lambda s: agg[s][0])
     achieved = agg[dom][2] / (agg[dom][0] * 1e-3) / 1e9
+    # the whole pair loop of the batch graph: algorithmic bytes of every
+    # transform and W pass of every instance over the graph's wall time
+    # (which also holds the dense tails)
+    loop_bytes = sum(v[2] for v in agg.values())
     result = {
         "metric": "orbital-pair Poisson solves/s over 16 uneven systems in one graph launch",
         "value": total_pairs / t_graph, "unit": "pair-solves/s", "n_gpus": 1,
@@ -400,14 +405,18 @@ def run_batch(args):
         "config": {"workload": "16 single-Gaussian water-density systems, grids %s, orbitals %s, "
                                "%d pairs in all; step = one batch build"
                                % ([sp.n for sp in specs], [sp.n_orb for sp in specs], total_pairs),
-                   "shapes": [list(p.tiling) for p in plans]},
+                   "shapes": [list(p.tiling) + [p.four_pass] for p in plans]},
+        "tuner": tuned,
         "lanes": lanes, "tiles_in_shared_passes": whole_tiles, "tiles_other": other_tiles,
         "graph_ms": 1000 * t_graph, "eager_branches_ms": 1000 * t_eager,
         "sequential_ms": 1000 * t_seq, "speedup_vs_sequential": t_seq / t_graph,
         "ex_bitwise_equal_to_sequential": bool(np.array_equal(ex_graph, ex_seq)),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "note": "all launches of the kernel over the batch, sequential profiled pass"},
+                     "note": "all launches of the kernel over the batch, sequential profiled pass",
+                     "batch_graph": {"alg_bytes": loop_bytes,
+                                     "achieved": loop_bytes / t_graph / 1e9,
+                                     "frac": loop_bytes / t_graph / 1e9 / HBM_PEAK_GBPS}},
         "stages_sequential": stages,
     }
     print(json.dumps(result), flush=True)
