@@ -37,6 +37,10 @@ STAGE_OF = [
 
 
 def stage_of(name: str) -> str:
+    if "k_batch_pass<" in name:
+        # second template argument: the pass (0 forward, 1 middle, 2 inverse z + W)
+        p = name.split("k_batch_pass<")[1].split(">")[0].split(",")[1].strip()
+        return {"0": "yz_fwd", "1": "x_poisson", "2": "w_accumulate"}.get(p, "other")
     if "k_lines" in name:
         # third template argument MODE: 0 Poisson (x), 1 energy, 2 y forward, 3 y inverse
         mode = name.split("k_lines<")[1].split(">")[0].split(",")[2].strip()
