@@ -766,14 +766,12 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
 
 // ------------------------------------------------------------------ y/z slabs, forward
 // Where a whole plane does not fit LDS, the forward y and z transforms of a
-// plane are still done in one pass, a slab of z positions at a time: every
-// slab's workgroup recomputes the first z step (N1-point DFTs) of all the
-// plane's rows, keeps the K1S = ZC / N2 of its N1 outputs per row that land
-// in its slab, finishes the z transform and the whole y transform there and
-// writes its ZC columns once, in position order S[x][ky][kz].  The orbital
-// rows come from the caches for all but the first slab; the scratch is
-// written once instead of written, read and written again by a z-row pass
-// and a y-line pass.
+// plane are still done in one pass, a slab of z positions at a time: of the
+// first z step (N1-point DFTs) of all the plane's rows, the K1S = ZC / N2
+// outputs per row that land in a slab go to LDS, where the z transform and
+// the whole y transform of the slab's ZC columns are finished and written
+// once, in position order S[x][ky][kz].  The scratch is written once instead
+// of written, read and written again by a z-row pass and a y-line pass.
 // The fewest slabs that fit (more slabs, for more workgroups per CU,
 // measured slower: the recomputed first step and orbital loads grow with
 // the slab count).
@@ -790,25 +788,51 @@ constexpr int slab_count() {
 template <typename T, int N>
 constexpr bool slab_ok() { return !plane_ok<T, N>() && slab_count<T, N>() > 0; }
 
-template <typename T>
-constexpr int slab_threads() { return sizeof(T) == 8 ? 768 : 1024; }
+// A workgroup takes SPW consecutive slabs of its plane from one first step:
+// the outputs of its first slab go to LDS, those of the others wait in
+// registers (at most 72 per thread with 512 FP64 threads, 48 with 768, 32
+// with 1024 FP32 threads: beyond that the kernels spill).  The first step is
+// recomputed SL / SPW times per plane.
+template <typename T, int SPW, int SL>
+constexpr int slab_threads() {
+  return sizeof(T) == 4 ? 1024 : (SPW == SL ? 512 : 768);
+}
 
 template <typename T, int N>
-__global__ __launch_bounds__(slab_threads<T>()) void k_slab_fwd(
+constexpr int slab_spw() {
+  constexpr int N2 = fft_split<N>::N2, SL = slab_count<T, N>();
+  if (SL == 0) return 1;
+  constexpr int K1S = N / SL / N2;
+  for (int spw = SL; spw > 1; --spw) {
+    if (SL % spw) continue;
+    const int nt = sizeof(T) == 4 ? 1024 : (spw == SL ? 512 : 768);
+    const int q = (N * N2 + nt - 1) / nt;
+    const int cap = sizeof(T) == 4 ? 32 : (spw == SL ? 72 : 48);
+    if ((spw - 1) * K1S * q * int(sizeof(cx<T>) / 4) <= cap) return spw;
+  }
+  return 1;
+}
+
+template <typename T, int N, int SPW>
+__global__ __launch_bounds__((slab_threads<T, SPW, slab_count<T, N>()>())) void k_slab_fwd(
     const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
     cx<T>* __restrict__ S, int npack, int64_t npts) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2;
   constexpr int SL = slab_count<T, N>(), ZC = N / SL, K1S = ZC / N2, PZ = ZC + 1;
-  constexpr int NT = slab_threads<T>();
-  static_assert(SL > 0 && ZC % N2 == 0, "a slab holds whole second-step blocks");
+  constexpr int NG = SL / SPW;                          // workgroups per plane
+  constexpr int NT = slab_threads<T, SPW, SL>();
+  constexpr int Q = (N * N2 + NT - 1) / NT;            // first-step tasks per thread
+  constexpr int KH = SPW > 1 ? (SPW - 1) * K1S : 1;    // outputs held per task
+  static_assert(SL > 0 && ZC % N2 == 0 && SL % SPW == 0, "whole second-step blocks per slab");
   __shared__ cx<T> lds[N * PZ];
   __shared__ cx<T> stw[N];
-  // item: the slabs of one (x, transform) plane are consecutive on one XCD
-  // (workgroup b runs on XCD b mod 8), so its orbital rows are in that L2
+  // item: (x, transform, slab group); the groups of one plane are
+  // consecutive on one XCD (workgroup b runs on XCD b mod 8), so its orbital
+  // rows are in that L2
   const int i = blockIdx.x;
-  const int r = i >> 3, sl = r % SL;
+  const int r = i >> 3, grp = r % NG;
   int x, p;
-  plane_item<T, N>((r / SL) * 8 + (i & 7), npack, x, p);
+  plane_item<T, N>((r / NG) * 8 + (i & 7), npack, x, p);
   const Pack pk = packs[p];
   const int tid = threadIdx.x;
   for (int k = tid; k < N; k += NT) stw[k] = tw[(k % N2) * (k / N2)];
@@ -817,62 +841,92 @@ __global__ __launch_bounds__(slab_threads<T>()) void k_slab_fwd(
   const T* __restrict__ pb = phi + (int64_t)pk.b * npts + plane;
   const T* __restrict__ pd = phi + (int64_t)(pk.c >= 0 ? pk.d : pk.b) * npts + plane;
   const T dmask = pk.c >= 0 ? T(1) : T(0);
-  const int k10 = sl * K1S;  // first step-1 output of the slab
+  cx<T> hold[Q][KH];
   __syncthreads();
-  // z step 1 over every row: tasks (y, t2), t2 fastest; keep outputs k10 ..
-  for (int task = tid; task < N * N2; task += NT) {
-    const int y = task / N2, t2 = task % N2;
-    cx<T> v[N1];
+  // z step 1 over every row: tasks (y, t2), t2 fastest; the outputs of the
+  // group's first slab go to LDS, those of its other slabs to registers
+  // (static indices: the group is a compile-time case, the test uniform)
+  sfor<0, NG>([&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    constexpr int K0 = G * SPW * K1S;  // first step-1 output of the group
+    if (grp == G) {
 #pragma unroll
-    for (int j1 = 0; j1 < N1; ++j1) {
-      const int off = y * N + t2 + N2 * j1;
-      const T fa = pa[off];
-      v[j1] = {fa * pb[off], fa * (dmask * pd[off])};
+      for (int q = 0; q < Q; ++q) {
+        const int task = tid + q * NT;
+        if (task < N * N2) {
+          const int y = task / N2, t2 = task % N2;
+          cx<T> v[N1];
+#pragma unroll
+          for (int j1 = 0; j1 < N1; ++j1) {
+            const int off = y * N + t2 + N2 * j1;
+            const T fa = pa[off];
+            v[j1] = {fa * pb[off], fa * (dmask * pd[off])};
+          }
+          dft<N1, false>(v);
+#pragma unroll
+          for (int k1 = K0; k1 < K0 + SPW * K1S; ++k1) {
+            const cx<T> w = k1 == 0 ? v[0] : cmul(v[k1], stw[k1 * N2 + t2]);
+            if (k1 < K0 + K1S) lds[y * PZ + t2 + N2 * (k1 - K0)] = w;
+            else hold[q][k1 - K0 - K1S] = w;
+          }
+        }
+      }
     }
-    dft<N1, false>(v);
-    // static register indices; the slab test is uniform across the workgroup
+  });
+  // the rest of the transform for one slab whose first-step outputs are in LDS
+  auto finish = [&](int sl) __attribute__((always_inline)) {
+    __syncthreads();
+    // z step 2 of the slab's blocks: tasks (y, k), y fastest
+    for (int task = tid; task < N * K1S; task += NT) {
+      const int y = task % N, k = task / N;
+      cx<T> v[N2];
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      if (k1 >= k10 && k1 < k10 + K1S)
-        lds[y * PZ + t2 + N2 * (k1 - k10)] = k1 == 0 ? v[0] : cmul(v[k1], stw[k1 * N2 + t2]);
+      for (int t = 0; t < N2; ++t) v[t] = lds[y * PZ + t + N2 * k];
+      dft<N2, false>(v);
+#pragma unroll
+      for (int t = 0; t < N2; ++t) lds[y * PZ + t + N2 * k] = v[t];
     }
-  }
-  __syncthreads();
-  // z step 2 of the slab's blocks: tasks (y, k), y fastest
-  for (int task = tid; task < N * K1S; task += NT) {
-    const int y = task % N, k = task / N;
-    cx<T> v[N2];
+    __syncthreads();
+    // y step 1: tasks (pz, u2), pz fastest
+    for (int task = tid; task < ZC * N2; task += NT) {
+      const int pz = task % ZC, u2 = task / ZC;
+      cx<T> v[N1];
 #pragma unroll
-    for (int t = 0; t < N2; ++t) v[t] = lds[y * PZ + t + N2 * k];
-    dft<N2, false>(v);
+      for (int j1 = 0; j1 < N1; ++j1) v[j1] = lds[(u2 + N2 * j1) * PZ + pz];
+      dft<N1, false>(v);
 #pragma unroll
-    for (int t = 0; t < N2; ++t) lds[y * PZ + t + N2 * k] = v[t];
-  }
-  __syncthreads();
-  // y step 1: tasks (pz, u2), pz fastest
-  for (int task = tid; task < ZC * N2; task += NT) {
-    const int pz = task % ZC, u2 = task / ZC;
-    cx<T> v[N1];
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[k1 * N2 + u2]);
 #pragma unroll
-    for (int j1 = 0; j1 < N1; ++j1) v[j1] = lds[(u2 + N2 * j1) * PZ + pz];
-    dft<N1, false>(v);
+      for (int k1 = 0; k1 < N1; ++k1) lds[(u2 + N2 * k1) * PZ + pz] = v[k1];
+    }
+    __syncthreads();
+    // y step 2 -> global: tasks (pz, k1), pz fastest (a slab row is contiguous)
+    cx<T>* __restrict__ out = S + (int64_t)p * npts + plane + sl * ZC;
+    for (int task = tid; task < ZC * N1; task += NT) {
+      const int pz = task % ZC, k1 = task / ZC;
+      cx<T> v[N2];
 #pragma unroll
-    for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[k1 * N2 + u2]);
+      for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * PZ + pz];
+      dft<N2, false>(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) lds[(u2 + N2 * k1) * PZ + pz] = v[k1];
-  }
-  __syncthreads();
-  // y step 2 -> global: tasks (pz, k1), pz fastest (a slab row is contiguous)
-  cx<T>* __restrict__ out = S + (int64_t)p * npts + plane + sl * ZC;
-  for (int task = tid; task < ZC * N1; task += NT) {
-    const int pz = task % ZC, k1 = task / ZC;
-    cx<T> v[N2];
+      for (int t = 0; t < N2; ++t) st_stream(&out[(int64_t)(t + N2 * k1) * N + pz], v[t]);
+    }
+  };
+  finish(grp * SPW);
+  sfor<1, SPW>([&](auto sc) {
+    constexpr int h = decltype(sc)::value;
+    __syncthreads();  // the previous slab read out of LDS
 #pragma unroll
-    for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * PZ + pz];
-    dft<N2, false>(v);
+    for (int q = 0; q < Q; ++q) {
+      const int task = tid + q * NT;
+      if (task < N * N2) {
+        const int y = task / N2, t2 = task % N2;
 #pragma unroll
-    for (int t = 0; t < N2; ++t) st_stream(&out[(int64_t)(t + N2 * k1) * N + pz], v[t]);
-  }
+        for (int k = 0; k < K1S; ++k) lds[y * PZ + t2 + N2 * k] = hold[q][(h - 1) * K1S + k];
+      }
+    }
+    finish(grp * SPW + h);
+  });
 }
 
 // ------------------------------------------------------------------ z rows (fallback)
@@ -1515,9 +1569,10 @@ static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs
                          g.npts);
   } else if constexpr (slab_ok<T, N>()) {
     if (zxy) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_slab_fwd<T, N>), dim3(N * npack * slab_count<T, N>()),
-                       dim3(slab_threads<T>()), 0, s, static_cast<const T*>(phi), packs, tw,
-                       static_cast<cx<T>*>(S), npack, g.npts);
+    constexpr int SPW = slab_spw<T, N>(), SL = slab_count<T, N>();
+    hipLaunchKernelGGL((k_slab_fwd<T, N, SPW>), dim3(N * npack * (SL / SPW)),
+                       dim3(slab_threads<T, SPW, SL>()), 0, s, static_cast<const T*>(phi),
+                       packs, tw, static_cast<cx<T>*>(S), npack, g.npts);
   } else {
     if (zxy) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_rows_fwd<T, N>), dim3((N * N / kRowsPerBlock) * npack),
