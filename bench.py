@@ -39,71 +39,53 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_water32_n96.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_07670_amd", "csrc", "poisson.hip")
 
 
-def plane_fits(n, bulk):
-    """Does one (y, z) plane (plus twiddles) of the bulk type fit the 160 KiB LDS?"""
-    return (n * (n + 1) + n) * 2 * bulk + 64 <= 163840
-
-
-def three_pass_fits(n, bulk, block):
-    """Do the three-pass kernels fit (plane in LDS; 8 n threads and
-    block/2 x 8 z lines in the last pass)?"""
-    rows = 8
-    return (plane_fits(n, bulk) and rows * n <= 1024
-            and ((block // 2) * rows * (n + 1) + n) * 2 * bulk + 64 <= 163840)
-
-
-def rows_fused_fits(n, bulk, block):
-    """Large grids (no plane in LDS): does the fused inverse-z/W pass fit
-    (4 n threads, block/2 x 4 z rows in LDS)?"""
-    return (not plane_fits(n, bulk) and 4 * n <= 1024
-            and ((block // 2) * 4 * (n + 1) + n) * 2 * bulk + 64 <= 163840)
-
-
-def tile_plan(n_orb, block, n=None, bulk=8, four_pass=False):
-    """(bi, bj, diag, npack, fused) for every tile of the unmasked schedule;
-    `fused`: the tile's inverse z transform is fused with the W update (a
-    full tile; three passes where a plane fits, else the large-grid
-    schedule)."""
+def tile_plan(n_orb, block, full_kind="three_pass"):
+    """(bi, bj, diag, npack, kind) for every tile of the unmasked schedule;
+    kind: the passes the tile takes ("three_pass", "rows_fused" or
+    "four_pass"; full tiles take the plan's full-tile schedule, the library's
+    ace_plan_schedule, the others four passes)."""
     out = []
     nb = (n_orb + block - 1) // block
-    fits = n is not None and not four_pass and (three_pass_fits(n, bulk, block)
-                                                or rows_fused_fits(n, bulk, block))
     for I in range(nb):
         for J in range(I, nb):
             bi = min(block, n_orb - I * block)
             bj = min(block, n_orb - J * block)
             # two pairs of one row share a transform; a row's odd leftover is alone
             rows = [bi - a for a in range(bi)] if I == J else [bj] * bi
-            three = fits and bi == block and bj == block
-            out.append((bi, bj, I == J, sum((r + 1) // 2 for r in rows), three))
+            kind = full_kind if bi == block and bj == block else "four_pass"
+            out.append((bi, bj, I == J, sum((r + 1) // 2 for r in rows), kind))
     return out
+
+
+def plan_tiles(plan):
+    kind, plane = plan.schedule()
+    return tile_plan(plan.n_orb, plan.tiling[0], kind), plane
 
 
 def algorithmic_bytes(stage, tiles, npts, bulk, plane=True):
     """Compulsory HBM bytes of one step's launches of `stage` in this design.
 
-    Per packed transform (two pairs) and grid point: yz_fwd writes one
-    complex value; x_poisson (the middle pass) reads and writes one; yz_inv
-    (tiles without the fused inverse z; on large grids the inverse y lines of
-    fused tiles) reads and writes one; w_accumulate reads one.
+    Per packed transform (two pairs) and grid point, c = one complex value:
+    yz_fwd writes c (a plane, or slab by slab where a plane does not fit
+    LDS); x_poisson (the middle pass: x, and on three-pass tiles the inverse
+    y too) reads and writes c; yz_inv reads and writes c on four-pass tiles
+    (twice where a plane does not fit: inverse y lines, then z rows) and on
+    row-fused tiles (the inverse y lines); w_accumulate reads c.
     Orbital traffic is counted once per tile: yz_fwd reads the tile's
     orbitals (8 B/pt each); w_accumulate reads them and reads + writes their
     W rows (24 B/pt each).
     """
     c = 2 * bulk
-    # where the plane does not fit, the y/z stage is a row pass plus a column
-    # pass: one extra read and write of the complex grid each way
-    extra = 0 if plane else 2 * c
     tot = 0
-    for bi, bj, diag, npack, fused in tiles:
+    for bi, bj, diag, npack, kind in tiles:
         orbs = bi if diag else bi + bj
         if stage == "yz_fwd":
-            tot += (npack * (c + extra) + orbs * 8) * npts
+            tot += (npack * c + orbs * 8) * npts
         elif stage == "yz_inv":
-            if fused:
-                tot += 0 if plane else npack * 2 * c * npts
-            else:
-                tot += npack * (2 * c + extra) * npts
+            if kind == "rows_fused":
+                tot += npack * 2 * c * npts
+            elif kind == "four_pass":
+                tot += npack * (2 * c if plane else 4 * c) * npts
         elif stage == "x_poisson":
             tot += npack * 2 * c * npts
         elif stage == "w_accumulate":
@@ -380,12 +362,12 @@ def run_batch(args):
     for p, sp in zip(plans, specs):
         prof = p.profile_read()
         p.set_profiling(False)
-        tiles = tile_plan(sp.n_orb, p.tiling[0], sp.n, bulk, p.four_pass)
+        tiles, plane = plan_tiles(p)
         for s in mem_stages:
             ms, cnt = prof[s]
             agg[s][0] += ms
             agg[s][1] += cnt
-            agg[s][2] += algorithmic_bytes(s, tiles, sp.n ** 3, bulk, plane_fits(sp.n, bulk))
+            agg[s][2] += algorithmic_bytes(s, tiles, sp.n ** 3, bulk, plane)
     stages = {s: {"ms": round(v[0], 3), "launches": v[1],
                   "alg_GBps": v[2] / (v[0] * 1e-3) / 1e9 if v[0] else None}
               for s, v in agg.items()}
@@ -589,7 +571,7 @@ def main():
     ceilings = None if args.no_ceilings else measure_ceilings(torch, dev)
 
     bulk = 8 if args.precision == "fp64" else 4
-    tiles = tile_plan(spec.n_orb, plan.tiling[0], spec.n, bulk, plan.four_pass)
+    tiles, plane = plan_tiles(plan)
     npts = spec.n ** 3
     mem_stages = ["yz_fwd", "x_poisson", "yz_inv", "w_accumulate"]
     stages = {}
@@ -598,7 +580,7 @@ def main():
             stages[name] = {"ms_per_step": ms / args.steps, "launches_per_step": cnt // args.steps}
     for name in mem_stages:
         if name in stages:
-            ab = algorithmic_bytes(name, tiles, npts, bulk, plane_fits(spec.n, bulk))
+            ab = algorithmic_bytes(name, tiles, npts, bulk, plane)
             launch_ms = stages[name]["ms_per_step"] / stages[name]["launches_per_step"]
             gbps = ab / (stages[name]["ms_per_step"] * 1e-3) / 1e9
             stages[name]["alg_GBps"] = gbps
@@ -649,7 +631,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_text(spec, args.precision),
                    "n_orb": spec.n_orb, "grid": spec.n, "pairs": spec.n_pairs,
-                   "tiling": list(plan.tiling)},
+                   "tiling": list(plan.tiling), "full_tiles": plan.schedule()[0]},
         "roofline": roofline,
         "pair_loop_ms": pair_loop_ms,
         "profiled_ms_per_step": 1000.0 * (tp1 - tp0) / args.steps,

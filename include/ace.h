@@ -239,26 +239,41 @@ int ace_set_profiling(ace_plan *plan, int on);
 int ace_profile_read(ace_plan *plan, double *out_ms, int *out_count);
 
 /* Launch-shape knobs, for the tuner: orbital block of the pair tiles
- * (8 or 16), the packed transforms per forward/inverse launch (0 = a whole
- * tile) and the x-pass pencils per workgroup (8, 16 or 32 dividing n; 0 =
- * the default).  chunk and pencils change no result bit; block changes
+ * (8 or 16; a new plan takes 16, or 8 where only block 8 has the three-pass
+ * schedule: FP64 120^3 and 128^3), the packed transforms per forward/inverse
+ * launch (0 = a whole tile) and the x-pass pencils per workgroup (8, 16 or
+ * 32 dividing n; 0 = the default).  chunk and pencils change no result bit; block changes
  * which pairs share a transform and the order of the W sums, so results move
  * by rounding only.  block changes ace_workspace_bytes (the scratch holds
  * one tile's transforms: block^2 / 2 complex grids).
  * ACE_ERR_ARG for a value outside these sets. */
 int ace_plan_set_tiling(ace_plan *plan, int block, int chunk, int pencils);
+/* The plan's current launch shape (any pointer may be NULL). */
+int ace_plan_tiling(const ace_plan *plan, int *block, int *chunk, int *pencils);
 
 /* Transform schedule.  ACE_SCHEDULE_AUTO: full pair tiles (block x block
  * orbitals, every pair kept; block 8 or 16) take three passes over the
  * scratch grids where the grid's plane fits a workgroup's LDS (FP64 n <= 96,
- * FP32 n <= 128) and five where it does not; in both the inverse z transform
- * feeds the W update directly.  Every other tile takes four passes (inverse
- * y/z written back, then the W update).
+ * FP32 n <= 128), or where a workgroup can take a plane slab by slab
+ * (FP64 120^3 and 128^3, block 8), and four elsewhere; in all of these the
+ * inverse z transform feeds the W update directly.  Every other tile takes
+ * four passes with the W update a pass of its own.
  * ACE_SCHEDULE_FOUR_PASS: four passes everywhere.  Both give the same result
  * up to rounding (the order of the W sums differs). */
 #define ACE_SCHEDULE_AUTO 0
 #define ACE_SCHEDULE_FOUR_PASS 1
 int ace_plan_set_schedule(ace_plan *plan, int schedule);
+/* The passes the plan's current shape and schedule give (host-side, for
+ * byte accounting): *full_tiles is ACE_TILES_THREE_PASS (forward, middle,
+ * inverse z with W), ACE_TILES_ROWS_FUSED (forward, x, inverse y, inverse z
+ * rows with W) or ACE_TILES_FOUR_PASS (forward, x, inverse y/z, W), the
+ * schedule of full tiles; other tiles take four passes.  *plane is 1 where
+ * a (y, z) plane fits LDS and 0 where the forward pass works slab by slab
+ * and a four-pass inverse y/z is a line pass plus a row pass. */
+#define ACE_TILES_THREE_PASS 0
+#define ACE_TILES_ROWS_FUSED 1
+#define ACE_TILES_FOUR_PASS 2
+int ace_plan_schedule(const ace_plan *plan, int *full_tiles, int *plane);
 
 /* ---- Batches of independent systems (uneven grids and orbital counts).
  *

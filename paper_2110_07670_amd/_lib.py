@@ -24,7 +24,7 @@ STAGE_NAMES = ["yz_fwd", "x_poisson", "yz_inv", "w_accumulate", "m_product", "ch
 EXPORTS = ["ace_plan_create", "ace_plan_destroy", "ace_workspace_bytes",
            "ace_apply_workspace_bytes", "ace_build", "ace_apply", "exx_energy",
            "ace_error_string", "ace_last_hip_error", "ace_set_profiling", "ace_profile_read",
-           "ace_plan_set_tiling", "ace_plan_set_schedule", "ace_overlap_integrals", "ace_wannier", "ace_mlp_screen",
+           "ace_plan_set_tiling", "ace_plan_tiling", "ace_plan_set_schedule", "ace_plan_schedule", "ace_overlap_integrals", "ace_wannier", "ace_mlp_screen",
            "ace_mlp_weight_count", "ace_batch_create", "ace_batch_destroy",
            "ace_batch_workspace_bytes", "ace_batch_build", "ace_batch_lanes", "scdm_workspace_bytes",
            "scdm_preselect", "scdm_localize", "ace_apply_noalloc", "ace_screen_mask",
@@ -101,6 +101,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ace_profile_read.restype = i
     lib.ace_plan_set_tiling.argtypes = [vp, i, i, i]
     lib.ace_plan_set_tiling.restype = i
+    lib.ace_plan_tiling.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.ace_plan_tiling.restype = i
+    lib.ace_plan_schedule.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
+    lib.ace_plan_schedule.restype = i
     lib.ace_plan_set_schedule.argtypes = [vp, i]
     lib.ace_plan_set_schedule.restype = i
     lib.ace_overlap_integrals.argtypes = [vp, vp, vp, sz, vp, vp]
@@ -236,7 +240,10 @@ class Plan:
         self.grid = tuple(int(v) for v in g)
         self.precision = d.precision
         self.npts = g[0] * g[1] * g[2]
-        self.tiling = (16, 0, 0)
+        blk, ch, pen = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib.ace_plan_tiling(h, ctypes.byref(blk), ctypes.byref(ch), ctypes.byref(pen)),
+               "ace_plan_tiling")
+        self.tiling = (blk.value, ch.value, pen.value)
         self.four_pass = False
 
     @property
@@ -272,6 +279,14 @@ class Plan:
         _check(load().ace_plan_set_schedule(self._h, 1 if four_pass else 0),
                "ace_plan_set_schedule")
         self.four_pass = bool(four_pass)
+
+    def schedule(self):
+        """(full-tile schedule: "three_pass", "rows_fused" or "four_pass",
+        whether a (y, z) plane fits LDS) for the current shape."""
+        kind, plane = ctypes.c_int(), ctypes.c_int()
+        _check(load().ace_plan_schedule(self._h, ctypes.byref(kind), ctypes.byref(plane)),
+               "ace_plan_schedule")
+        return ["three_pass", "rows_fused", "four_pass"][kind.value], bool(plane.value)
 
     def set_profiling(self, on: bool):
         _check(load().ace_set_profiling(self._h, 1 if on else 0), "ace_set_profiling")

@@ -715,7 +715,10 @@ int ace_plan_create(ace_plan** plan, const ace_desc* d) {
   p->npts = (int64_t)p->n * p->n * p->n;
   p->omega = d->cell[0] * d->cell[1] * d->cell[2];
   p->dV = p->omega / (double)p->npts;
-  p->block = 16;
+  // block 16, unless only block 8 has the three-pass schedule on this grid
+  p->block = (!acex::three_pass_ok(p->n, p->prec, 16) && acex::three_pass_ok(p->n, p->prec, 8))
+                 ? 8
+                 : 16;
   p->chunk = 0;
   p->pencils = 0;
   p->schedule = ACE_SCHEDULE_AUTO;
@@ -752,6 +755,27 @@ int ace_plan_set_tiling(ace_plan* plan, int block, int chunk, int pencils) {
   plan->chunk = chunk;
   plan->pencils = pencils;
   layout(plan);
+  return ACE_OK;
+}
+
+int ace_plan_tiling(const ace_plan* plan, int* block, int* chunk, int* pencils) {
+  if (!plan) return ACE_ERR_ARG;
+  if (block) *block = plan->block;
+  if (chunk) *chunk = plan->chunk;
+  if (pencils) *pencils = plan->pencils;
+  return ACE_OK;
+}
+
+int ace_plan_schedule(const ace_plan* plan, int* full_tiles, int* plane) {
+  if (!plan) return ACE_ERR_ARG;
+  const bool fuse_ok = plan->schedule == ACE_SCHEDULE_AUTO;
+  int kind = ACE_TILES_FOUR_PASS;
+  if (fuse_ok && acex::three_pass_ok(plan->n, plan->prec, plan->block))
+    kind = ACE_TILES_THREE_PASS;
+  else if (fuse_ok && acex::fused_rows_ok(plan->n, plan->prec, plan->block))
+    kind = ACE_TILES_ROWS_FUSED;
+  if (full_tiles) *full_tiles = kind;
+  if (plane) *plane = acex::plane_fits(plan->n, plan->prec) ? 1 : 0;
   return ACE_OK;
 }
 

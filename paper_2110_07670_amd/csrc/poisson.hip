@@ -513,23 +513,89 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_mid(
   plane_mid_item<T, N, plane_threads<N>()>(S, tw, npts, g0, g1, g2, kscale, blockIdx.x, lds, stw);
 }
 
+// ------------------------------------------------------------------ slab sizes
+// The fewest slabs that fit (more slabs, for more workgroups per CU,
+// measured slower: the recomputed first step and orbital loads grow with
+// the slab count).
+template <typename T, int N>
+constexpr int slab_count() {
+  constexpr int N2 = fft_split<N>::N2;
+  for (int sl = 2; sl <= 8; ++sl)
+    if (N % sl == 0 && (N / sl) % N2 == 0 &&
+        ((long)N * (N / sl + 1) + N) * (long)sizeof(cx<T>) + 64 <= kLdsBytes)
+      return sl;
+  return 0;
+}
+
+template <typename T, int N>
+constexpr bool slab_ok() { return !plane_ok<T, N>() && slab_count<T, N>() > 0; }
+
+// A workgroup takes SPW consecutive slabs of its plane from one first step:
+// the outputs of its first slab go to LDS, those of the others wait in
+// registers (at most 72 per thread with 512 FP64 threads, 48 with 768, 32
+// with 1024 FP32 threads: beyond that the kernels spill).  The first step is
+// recomputed SL / SPW times per plane.
+template <typename T, int SPW, int SL>
+constexpr int slab_threads() {
+  return sizeof(T) == 4 ? 1024 : (SPW == SL ? 512 : 768);
+}
+
+template <typename T, int N>
+constexpr int slab_spw() {
+  constexpr int N2 = fft_split<N>::N2, SL = slab_count<T, N>();
+  if (SL == 0) return 1;
+  constexpr int K1S = N / SL / N2;
+  for (int spw = SL; spw > 1; --spw) {
+    if (SL % spw) continue;
+    const int nt = sizeof(T) == 4 ? 1024 : (spw == SL ? 512 : 768);
+    const int q = (N * N2 + nt - 1) / nt;
+    const int cap = sizeof(T) == 4 ? 32 : (spw == SL ? 72 : 48);
+    if ((spw - 1) * K1S * q * int(sizeof(cx<T>) / 4) <= cap) return spw;
+  }
+  return 1;
+}
+
+template <typename T, int N>
+constexpr bool slab3_ok() {
+  return slab_ok<T, N>() && slab_spw<T, N>() == slab_count<T, N>();
+}
+
 // Rows of y per inverse-z workgroup (one workgroup: rows x N points).  Eight
 // rows read 128 B (FP64) of each scratch row per transform; four FP64 rows
 // (64 B segments, two workgroups per CU) measured slower, even with the two
-// halves of each segment dispatched back to back on one XCD.
+// halves of each segment dispatched back to back on one XCD.  Grids past
+// 128 (more than 1024 points in eight rows) take four.
 // ROWS: the large-grid schedule, whose scratch is S[x][y][kz] (each z row
 // contiguous, so four rows per workgroup read whole rows).
-template <typename T, bool ROWS = false>
-constexpr int zinv_rows() { return ROWS ? 4 : 8; }
+template <typename T, int N, bool ROWS = false>
+constexpr int zinv_rows() { return (ROWS || 8 * N > 1024) ? 4 : 8; }
 
 template <typename T, int N, bool ROWS = false>
-constexpr int zinv_threads() { return zinv_rows<T, ROWS>() * N; }
+constexpr int zinv_threads() { return zinv_rows<T, N, ROWS>() * N; }
 
+template <typename T, int N, int B, bool ROWS>
+constexpr bool zinv_fits() {
+  return zinv_threads<T, N, ROWS>() <= 1024 &&
+         ((long)(B / 2) * zinv_rows<T, N, ROWS>() * (N + 1) + N) * (long)sizeof(cx<T>) + 64 <=
+             kLdsBytes;
+}
+
+// The plane form (scratch S[kz][x][y]) serves the three-pass schedules, of
+// plane-fitting grids and of slab grids; the row form (S[x][y][kz]) the
+// large-grid four-pass one where those do not apply.
+// On slab grids the plane form also needs its registers: above 768 threads
+// (128 registers each) the block-16 form spills, so there only block 8; and
+// eight rows per workgroup (at 160^3 FP32 the four-row form, 32-byte
+// segments, took 1.44 s per 512-orbital build against 0.83 s for the row
+// form, more than the middle pass saves).
 template <typename T, int N, int B, bool ROWS = false>
 constexpr bool zinv_ok() {
-  return (ROWS ? !plane_ok<T, N>() : plane_ok<T, N>()) && zinv_threads<T, N, ROWS>() <= 1024 &&
-         ((long)(B / 2) * zinv_rows<T, ROWS>() * (N + 1) + N) * (long)sizeof(cx<T>) + 64 <=
-             kLdsBytes;
+  constexpr bool three =
+      zinv_fits<T, N, B, false>() &&
+      (plane_ok<T, N>() || (slab3_ok<T, N>() && zinv_rows<T, N, false>() == 8 &&
+                            (B == 8 || zinv_threads<T, N, false>() <= 768)));
+  if constexpr (!ROWS) return three;
+  else return !plane_ok<T, N>() && !three && zinv_fits<T, N, B, true>();
 }
 
 // A workgroup owns the points (x, y0 .. y0 + YC - 1, all z) of a full B x B tile and
@@ -548,7 +614,7 @@ __device__ __forceinline__ void zinv_item(const cx<T>* __restrict__ S,
                                           double alpha, int64_t npts, int bid,
                                           cx<T>* __restrict__ lds, cx<T>* __restrict__ stw) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2, P = N + 1;
-  constexpr int G = B / 2, YC = zinv_rows<T, ROWS>();
+  constexpr int G = B / 2, YC = zinv_rows<T, N, ROWS>();
   constexpr int ACT = zinv_threads<T, N, ROWS>();  // threads that own a point
   static_assert(NT >= ACT, "a thread per point");
   // kz positions and rows in the scratch: S[kz][x][y] (kz stride N^2, rows
@@ -758,7 +824,7 @@ template <typename T, int N, int B, bool DIAG, bool ROWS>
 __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
     const cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, const T* __restrict__ phi,
     double* __restrict__ W, const int* __restrict__ orbs, double alpha, int64_t npts) {
-  __shared__ cx<T> lds[(B / 2) * zinv_rows<T, ROWS>() * (N + 1)];
+  __shared__ cx<T> lds[(B / 2) * zinv_rows<T, N, ROWS>() * (N + 1)];
   __shared__ cx<T> stw[N];
   zinv_item<T, N, B, DIAG, ROWS, zinv_threads<T, N, ROWS>()>(S, tw, phi, W, orbs, alpha, npts,
                                                                blockIdx.x, lds, stw);
@@ -772,48 +838,11 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
 // the whole y transform of the slab's ZC columns are finished and written
 // once, in position order S[x][ky][kz].  The scratch is written once instead
 // of written, read and written again by a z-row pass and a y-line pass.
-// The fewest slabs that fit (more slabs, for more workgroups per CU,
-// measured slower: the recomputed first step and orbital loads grow with
-// the slab count).
-template <typename T, int N>
-constexpr int slab_count() {
-  constexpr int N2 = fft_split<N>::N2;
-  for (int sl = 2; sl <= 8; ++sl)
-    if (N % sl == 0 && (N / sl) % N2 == 0 &&
-        ((long)N * (N / sl + 1) + N) * (long)sizeof(cx<T>) + 64 <= kLdsBytes)
-      return sl;
-  return 0;
-}
 
-template <typename T, int N>
-constexpr bool slab_ok() { return !plane_ok<T, N>() && slab_count<T, N>() > 0; }
 
-// A workgroup takes SPW consecutive slabs of its plane from one first step:
-// the outputs of its first slab go to LDS, those of the others wait in
-// registers (at most 72 per thread with 512 FP64 threads, 48 with 768, 32
-// with 1024 FP32 threads: beyond that the kernels spill).  The first step is
-// recomputed SL / SPW times per plane.
-template <typename T, int SPW, int SL>
-constexpr int slab_threads() {
-  return sizeof(T) == 4 ? 1024 : (SPW == SL ? 512 : 768);
-}
-
-template <typename T, int N>
-constexpr int slab_spw() {
-  constexpr int N2 = fft_split<N>::N2, SL = slab_count<T, N>();
-  if (SL == 0) return 1;
-  constexpr int K1S = N / SL / N2;
-  for (int spw = SL; spw > 1; --spw) {
-    if (SL % spw) continue;
-    const int nt = sizeof(T) == 4 ? 1024 : (spw == SL ? 512 : 768);
-    const int q = (N * N2 + nt - 1) / nt;
-    const int cap = sizeof(T) == 4 ? 32 : (spw == SL ? 72 : 48);
-    if ((spw - 1) * K1S * q * int(sizeof(cx<T>) / 4) <= cap) return spw;
-  }
-  return 1;
-}
-
-template <typename T, int N, int SPW>
+// ZXY: write S[kz][x][ky] (the large-grid three-pass schedule) instead of
+// S[x][ky][kz], through LDS so that the stores run along ky.
+template <typename T, int N, int SPW, bool ZXY>
 __global__ __launch_bounds__((slab_threads<T, SPW, slab_count<T, N>()>())) void k_slab_fwd(
     const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
     cx<T>* __restrict__ S, int npack, int64_t npts) {
@@ -900,16 +929,36 @@ __global__ __launch_bounds__((slab_threads<T, SPW, slab_count<T, N>()>())) void 
       for (int k1 = 0; k1 < N1; ++k1) lds[(u2 + N2 * k1) * PZ + pz] = v[k1];
     }
     __syncthreads();
-    // y step 2 -> global: tasks (pz, k1), pz fastest (a slab row is contiguous)
-    cx<T>* __restrict__ out = S + (int64_t)p * npts + plane + sl * ZC;
-    for (int task = tid; task < ZC * N1; task += NT) {
-      const int pz = task % ZC, k1 = task / ZC;
-      cx<T> v[N2];
+    if constexpr (!ZXY) {
+      // y step 2 -> global: tasks (pz, k1), pz fastest (a slab row is contiguous)
+      cx<T>* __restrict__ out = S + (int64_t)p * npts + plane + sl * ZC;
+      for (int task = tid; task < ZC * N1; task += NT) {
+        const int pz = task % ZC, k1 = task / ZC;
+        cx<T> v[N2];
 #pragma unroll
-      for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * PZ + pz];
-      dft<N2, false>(v);
+        for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * PZ + pz];
+        dft<N2, false>(v);
 #pragma unroll
-      for (int t = 0; t < N2; ++t) st_stream(&out[(int64_t)(t + N2 * k1) * N + pz], v[t]);
+        for (int t = 0; t < N2; ++t) st_stream(&out[(int64_t)(t + N2 * k1) * N + pz], v[t]);
+      }
+    } else {
+      // y step 2 in place, then the slab leaves transposed, consecutive
+      // threads on consecutive ky (column reads of the odd-pitch rows)
+      for (int task = tid; task < ZC * N1; task += NT) {
+        const int pz = task % ZC, k1 = task / ZC;
+        cx<T> v[N2];
+#pragma unroll
+        for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * PZ + pz];
+        dft<N2, false>(v);
+#pragma unroll
+        for (int t = 0; t < N2; ++t) lds[(t + N2 * k1) * PZ + pz] = v[t];
+      }
+      __syncthreads();
+      cx<T>* __restrict__ out = S + (int64_t)p * npts + (int64_t)x * N;
+      for (int e = tid; e < N * ZC; e += NT) {
+        const int ky = e % N, pz = e / N;
+        st_stream(&out[(int64_t)(sl * ZC + pz) * N * N + ky], lds[ky * PZ + pz]);
+      }
     }
   };
   finish(grp * SPW);
@@ -926,6 +975,121 @@ __global__ __launch_bounds__((slab_threads<T, SPW, slab_count<T, N>()>())) void 
       }
     }
     finish(grp * SPW + h);
+  });
+}
+
+// Large-grid three-pass schedule: where a workgroup holds all slabs of a
+// plane (slab_spw == slab_count), the forward pass writes S[kz][x][ky] and
+// the middle pass below does, per kz plane [x][ky], slab by slab of ky:
+// forward x, Coulomb multiply, inverse x and the second inverse y step
+// (within the slab's blocks), keeping each thread's share of the slab in
+// registers; after the last slab the first inverse y step runs on the held
+// values and the plane leaves in natural y, in place.  The inverse z and W
+// pass is then the plane-fitting grids' one.
+
+template <typename T, int N>
+__global__ __launch_bounds__((slab_threads<T, slab_count<T, N>(), slab_count<T, N>()>())) void
+k_slab_mid(cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts, T g0,
+           T g1, T g2, T kscale) {
+  constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2;
+  constexpr int SL = slab_count<T, N>(), ZC = N / SL, K1S = ZC / N2, PZ = ZC + 1;
+  constexpr int NT = slab_threads<T, SL, SL>();
+  constexpr int Q = (N * N2 + NT - 1) / NT;   // final-step tasks (x, t2) per thread
+  constexpr int KH = (SL - 1) * K1S;          // values held per task
+  __shared__ cx<T> lds[N * PZ];
+  __shared__ cx<T> stw[N];
+  const int bid = blockIdx.x;
+  const int pz = bid % N, p = bid / N;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];
+  cx<T>* __restrict__ io = S + (int64_t)p * npts + (int64_t)pz * N * N;
+  const int kz = freq_of_pos<N>(pz);
+  cx<T> hold[Q][KH];
+  sfor<0, SL>([&](auto sc) {
+    constexpr int sl = decltype(sc)::value;
+    __syncthreads();  // twiddles in place / the previous slab read out of LDS
+    // x forward step 1 from global: tasks (py, t2), py fastest
+    for (int task = tid; task < ZC * N2; task += NT) {
+      const int py = task % ZC, t2 = task / ZC;
+      cx<T> v[N1];
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) v[j1] = io[(int64_t)(t2 + N2 * j1) * N + sl * ZC + py];
+      dft<N1, false>(v);
+#pragma unroll
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], stw[k1 * N2 + t2]);
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) lds[(t2 + N2 * k1) * PZ + py] = v[k1];
+    }
+    __syncthreads();
+    // x forward step 2, Coulomb multiply, x inverse step 2: tasks (py, k1)
+    for (int task = tid; task < ZC * N1; task += NT) {
+      const int py = task % ZC, k1 = task / ZC;
+      const int ky = freq_of_pos<N>(sl * ZC + py);
+      cx<T> v[N2];
+#pragma unroll
+      for (int t = 0; t < N2; ++t) v[t] = lds[(t + N2 * k1) * PZ + py];
+      dft<N2, false>(v);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2)
+        v[k2] = scale(v[k2], coulomb_k<T, N>(k1 + N1 * k2, ky, kz, g0, g1, g2, kscale));
+      dft<N2, true>(v);
+#pragma unroll
+      for (int t = 0; t < N2; ++t) lds[(t + N2 * k1) * PZ + py] = v[t];
+    }
+    __syncthreads();
+    // x inverse step 1 to natural x, in place: tasks (py, t2)
+    for (int task = tid; task < ZC * N2; task += NT) {
+      const int py = task % ZC, t2 = task / ZC;
+      cx<T> v[N1];
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[(t2 + N2 * k1) * PZ + py], stw[k1 * N2 + t2]);
+      dft<N1, true>(v);
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) lds[(t2 + N2 * j1) * PZ + py] = v[j1];
+    }
+    __syncthreads();
+    // y inverse step 2 within the slab's blocks: tasks (x, k), x fastest
+    for (int task = tid; task < N * K1S; task += NT) {
+      const int x = task % N, k = task / N;
+      cx<T> v[N2];
+#pragma unroll
+      for (int t = 0; t < N2; ++t) v[t] = lds[x * PZ + t + N2 * k];
+      dft<N2, true>(v);
+#pragma unroll
+      for (int t = 0; t < N2; ++t) lds[x * PZ + t + N2 * k] = v[t];
+    }
+    __syncthreads();
+    if constexpr (sl + 1 < SL) {
+      // this thread's tasks (x, t2), t2 fastest: the slab's K1S values
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int task = tid + q * NT;
+        if (task < N * N2) {
+          const int t2 = task % N2, x = task / N2;
+#pragma unroll
+          for (int k = 0; k < K1S; ++k) hold[q][sl * K1S + k] = lds[x * PZ + t2 + N2 * k];
+        }
+      }
+    } else {
+      // y inverse step 1 -> global, natural y, in place (every slab of the
+      // plane has been read): tasks (x, t2), t2 fastest
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int task = tid + q * NT;
+        if (task < N * N2) {
+          const int t2 = task % N2, x = task / N2;
+          cx<T> v[N1];
+#pragma unroll
+          for (int k1 = 0; k1 < N1; ++k1) {
+            const cx<T> u = k1 < KH ? hold[q][k1 < KH ? k1 : 0] : lds[x * PZ + t2 + N2 * (k1 - KH)];
+            v[k1] = cmulc(u, stw[k1 * N2 + t2]);
+          }
+          dft<N1, true>(v);
+#pragma unroll
+          for (int j1 = 0; j1 < N1; ++j1) io[(int64_t)x * N + t2 + N2 * j1] = v[j1];
+        }
+      }
+    }
   });
 }
 
@@ -1381,7 +1545,7 @@ __device__ __forceinline__ void batch_item(const BatchSeg& g, int local, cx<T>* 
                                    g.npts, T(g.g2[0]), T(g.g2[1]), T(g.g2[2]), T(g.kscale), local,
                                    smem, smem + N * (N + 1));
   } else {
-    cx<T>* stw = smem + (B / 2) * zinv_rows<T>() * (N + 1);
+    cx<T>* stw = smem + (B / 2) * zinv_rows<T, N>() * (N + 1);
     const cx<T>* S = static_cast<const cx<T>*>(g.S);
     const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
     const T* phi = static_cast<const T*>(g.phi);
@@ -1414,7 +1578,7 @@ template <typename T, int PASS, int N, int B>
 __global__ __launch_bounds__(batch_threads<N>())
 __attribute__((amdgpu_waves_per_eu(batch_waves<T, PASS, N, B>()))) void k_batch_pass(
     const BatchSeg* __restrict__ segs, int nseg, int total, int* __restrict__ counter) {
-  __shared__ cx<T> smem[PASS == 2 ? (B / 2) * zinv_rows<T>() * (N + 1) + N : N * (N + 1) + N];
+  __shared__ cx<T> smem[PASS == 2 ? (B / 2) * zinv_rows<T, N>() * (N + 1) + N : N * (N + 1) + N];
   if constexpr (PASS == 0) {
     FwdLane<T, N> q{segs, nseg, total, (int64_t)N * N * N};
     plane_fwd_loop<T, N, true, batch_threads<N>()>(q, static_cast<const cx<T>*>(segs[0].tw),
@@ -1448,7 +1612,7 @@ bool batch_ok(int n, int prec, int block) {
 }
 
 int batch_items(int pass, int n, int npack) {
-  return pass == 2 ? n * (n / zinv_rows<double>()) : n * npack;
+  return pass == 2 ? n * (n / 8) : n * npack;  // eight rows per item on these grids
 }
 
 // Workgroups of a batch pass resident per CU (LDS and registers), looked up
@@ -1568,11 +1732,19 @@ static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs
                          static_cast<const T*>(phi), packs, tw, static_cast<cx<T>*>(S), npack,
                          g.npts);
   } else if constexpr (slab_ok<T, N>()) {
-    if (zxy) return hipErrorInvalidValue;
     constexpr int SPW = slab_spw<T, N>(), SL = slab_count<T, N>();
-    hipLaunchKernelGGL((k_slab_fwd<T, N, SPW>), dim3(N * npack * (SL / SPW)),
-                       dim3(slab_threads<T, SPW, SL>()), 0, s, static_cast<const T*>(phi),
-                       packs, tw, static_cast<cx<T>*>(S), npack, g.npts);
+    if (zxy) {
+      if constexpr (slab3_ok<T, N>())
+        hipLaunchKernelGGL((k_slab_fwd<T, N, SPW, true>), dim3(N * npack * (SL / SPW)),
+                           dim3(slab_threads<T, SPW, SL>()), 0, s, static_cast<const T*>(phi),
+                           packs, tw, static_cast<cx<T>*>(S), npack, g.npts);
+      else
+        return hipErrorInvalidValue;
+    } else {
+      hipLaunchKernelGGL((k_slab_fwd<T, N, SPW, false>), dim3(N * npack * (SL / SPW)),
+                         dim3(slab_threads<T, SPW, SL>()), 0, s, static_cast<const T*>(phi),
+                         packs, tw, static_cast<cx<T>*>(S), npack, g.npts);
+    }
   } else {
     if (zxy) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_rows_fwd<T, N>), dim3((N * N / kRowsPerBlock) * npack),
@@ -1610,6 +1782,12 @@ static hipError_t mid_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
                        static_cast<cx<T>*>(S), static_cast<const cx<T>*>(g.tw), npack, g.npts,
                        T(g.g2[0]), T(g.g2[1]), T(g.g2[2]), T(g.kscale));
     return hipGetLastError();
+  } else if constexpr (slab3_ok<T, N>()) {
+    constexpr int SL = slab_count<T, N>();
+    hipLaunchKernelGGL((k_slab_mid<T, N>), dim3(N * npack), dim3(slab_threads<T, SL, SL>()), 0,
+                       s, static_cast<cx<T>*>(S), static_cast<const cx<T>*>(g.tw), npack, g.npts,
+                       T(g.g2[0]), T(g.g2[1]), T(g.g2[2]), T(g.kscale));
+    return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
@@ -1618,7 +1796,7 @@ template <typename T, int N, int B, bool ROWS>
 static hipError_t zinv_launch(const GridArgs& g, bool diag, const void* S, const void* phi,
                               double* W, const int* orbs, double alpha, hipStream_t s) {
   if constexpr (zinv_ok<T, N, B, ROWS>()) {
-    const dim3 grid(N * (N / zinv_rows<T, ROWS>())), block(zinv_threads<T, N, ROWS>());
+    const dim3 grid(N * (N / zinv_rows<T, N, ROWS>())), block(zinv_threads<T, N, ROWS>());
     if (diag)
       hipLaunchKernelGGL((k_zinv_acc<T, N, B, true, ROWS>), grid, block, 0, s,
                          static_cast<const cx<T>*>(S), static_cast<const cx<T>*>(g.tw),
@@ -1635,7 +1813,7 @@ static hipError_t zinv_launch(const GridArgs& g, bool diag, const void* S, const
 template <typename T, int N, int B>
 static hipError_t zinv_t(const GridArgs& g, bool diag, const void* S, const void* phi,
                          double* W, const int* orbs, double alpha, hipStream_t s) {
-  if constexpr (plane_ok<T, N>())
+  if constexpr (zinv_ok<T, N, B, false>())
     return zinv_launch<T, N, B, false>(g, diag, S, phi, W, orbs, alpha, s);
   else
     return zinv_launch<T, N, B, true>(g, diag, S, phi, W, orbs, alpha, s);

@@ -91,9 +91,10 @@ def test_supported_grids_plan_and_workspace(n, prec):
     lib = _lib.load()
     rc, h = _create(_desc(n=n, k=16, prec=prec))
     assert rc == 0
+    assert lib.ace_plan_set_tiling(h, 16, 0, 0) == 0
     ws = lib.ace_workspace_bytes(h)
     bulk = 16 if prec == 0 else 8
-    # at least the scratch of one orbital-pair tile and the overlap tables
+    # at least the scratch of one 16 x 16 orbital-pair tile and the overlap tables
     assert ws >= 128 * n ** 3 * bulk
     assert lib.ace_apply_workspace_bytes(h, 4) >= 4 * 16 * 8
     assert lib.ace_plan_set_tiling(h, 8, 4, 0) == 0
@@ -354,3 +355,16 @@ def test_binding_rejects_bad_batch_inputs(plan16):
         b.build_into([_cpu((4, 16, 16, 8))], out, ws)
     with pytest.raises(ValueError, match="device tensor"):
         b.build_into([phi], out, ws)
+
+
+@pytest.mark.parametrize("n,prec,block", [(96, "fp64", 16), (128, "fp32", 16), (128, "fp64", 8),
+                                          (120, "fp64", 8), (144, "fp64", 16), (160, "fp32", 16)])
+def test_new_plan_block_is_the_three_pass_one(n, prec, block):
+    """A new plan takes block 16 unless only block 8 has the three-pass
+    schedule (the slab grids FP64 120^3 and 128^3)."""
+    p = _lib.Plan(n, (10.0,) * 3, 24, prec, 0.25)
+    assert p.tiling == (block, 0, 0)
+    lib = _lib.load()
+    b = ctypes.c_int()
+    assert lib.ace_plan_tiling(p.handle, ctypes.byref(b), None, None) == 0 and b.value == block
+    assert lib.ace_plan_tiling(None, None, None, None) == _lib.ACE_ERR_ARG

@@ -89,10 +89,11 @@ def test_three_pass_repeatable(lib):
     assert np.array_equal(a["W"], b["W"]) and np.array_equal(a["xi"], b["xi"])
 
 
-@pytest.mark.parametrize("n", [96, 128])
+@pytest.mark.parametrize("n", [96, 128, 160])
 def test_three_pass_fp32_matches_four_pass(lib, n):
-    """FP32 bulk: the two schedules agree to FP32 rounding; both stay within
-    the FP32 bound against the FP64 build."""
+    """FP32 bulk, block 16: the two schedules agree to FP32 rounding; both
+    stay within the FP32 bound against the FP64 build (at 160^3 the automatic
+    schedule is the large-grid one: slab forward pass, row-form inverse z)."""
     _say("three-pass fp32 n=%d orbitals 32" % n)
     spec = synth.SystemSpec("t3f", 0.11 * n + 5.0, n, 32, "random", 0, (1.0, 1.4), 0.25, 500 + n)
     s = synth.build_system(spec)
@@ -104,12 +105,13 @@ def test_three_pass_fp32_matches_four_pass(lib, n):
     assert abs(three["ex"][0] - ref["ex"][0]) < 1e-6 * abs(ref["ex"][0])
 
 
-@pytest.mark.parametrize("n", [16, 24, 32, 40, 48, 64, 80, 96, 120, 128])
+@pytest.mark.parametrize("n", [16, 24, 32, 40, 48, 64, 80, 96, 120, 128, 144, 160])
 def test_three_pass_every_plane_grid_fp32_against_oracle(lib, n):
-    """FP32 bulk on every grid whose FP32 plane fits LDS (the three-pass
-    schedule), 16 orbitals in blocks of 8 (three full tiles): W and E_x within
-    the FP32 bounds of the FP64 oracle.  Covers the inverse-z workgroup order
-    on grids that whole 128-byte scratch segments do not tile (24, 40, 120)."""
+    """FP32 bulk, 16 orbitals in blocks of 8 (three full tiles), on every
+    grid whose FP32 plane fits LDS (the three-pass schedule) and on 144^3 and
+    160^3 (slab forward pass, row-form inverse z): W and E_x within the FP32
+    bounds of the FP64 oracle.  Covers the inverse-z workgroup order on grids
+    that whole 128-byte scratch segments do not tile (24, 40, 120)."""
     _say("three-pass fp32 n=%d orbitals 16 block 8 vs oracle" % n)
     spec = synth.SystemSpec("t3o", 0.11 * n + 5.0, n, 16, "random", 0, (1.0, 1.4), 0.25, 700 + n)
     s = synth.build_system(spec)
@@ -122,10 +124,12 @@ def test_three_pass_every_plane_grid_fp32_against_oracle(lib, n):
     assert abs(out["ex"][0] - ref["ex"]) < 1e-6 * abs(ref["ex"])
 
 
-@pytest.mark.parametrize("n", [120, 144])
+@pytest.mark.parametrize("n", [120, 128, 144])
 def test_fused_rows_large_grids_fp64(lib, n):
-    """Grids whose plane does not fit LDS: the large-grid schedule fuses the
-    inverse z rows with the W update on full tiles (blocks of 8 here)."""
+    """Grids whose plane does not fit LDS, full tiles in blocks of 8: 120^3
+    and 128^3 take the slab three-pass schedule (forward and middle passes a
+    slab of the plane at a time, the plane-form inverse z with W); 144^3
+    the large-grid schedule that fuses the inverse z rows with the W update."""
     _say("large-grid fused schedule fp64 n=%d orbitals 16 block 8" % n)
     L = 0.11 * n + 5.0
     spec = synth.SystemSpec("t3L", L, n, 16, "random", 0, (1.0, 1.4), 0.25, 600 + n)
