@@ -52,6 +52,7 @@ def stage_of(name: str) -> str:
 
 
 def _short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
     return name.split("(")[0].replace("void ", "")
 
 
@@ -79,14 +80,15 @@ CALIBRATION_KERNEL = "k_probe_rw"
 
 def calibration(fetch, write):
     """(fetch factor, write factor): true KiB / counter KiB for the 1 GiB
-    in-place streaming pass."""
+    in-place streaming pass (the first k_probe_rw dispatch of the run: the
+    HBM-ceiling probes that bench.py runs later use larger buffers)."""
     true_kib = float(1 << 20)
-    cf = [v for _, k, v, _ in fetch if CALIBRATION_KERNEL in k]
-    cw = [v for _, k, v, _ in write if CALIBRATION_KERNEL in k]
+    cf = sorted((d, v) for d, k, v, _ in fetch if CALIBRATION_KERNEL in k)
+    cw = sorted((d, v) for d, k, v, _ in write if CALIBRATION_KERNEL in k)
     if not cf or not cw:
         raise SystemExit("no %s dispatch in the counter runs (bench.py --copy-calibration)"
                          % CALIBRATION_KERNEL)
-    return true_kib / max(cf), true_kib / max(cw)
+    return true_kib / cf[0][1], true_kib / cw[0][1]
 
 
 def summarize(trace_db, fetch_db, write_db, out_md, command):
@@ -202,29 +204,39 @@ def derived(rec):
 
 
 def summarize_counters(out_md, title, command, dbs):
+    """One row per library kernel: dispatches, mean duration and the derived
+    fractions of the collected counters."""
     tab = counter_table(dbs)
-    cols = sorted({c for rec in tab.values() for c in rec if not c.startswith("_")})
+    cols = [("mfma_busy", "MFMA busy"), ("f64_mfma_tflops", "FP64 MFMA TFLOP/s"),
+            ("wait_any", "wait any / wave-cycle"), ("wait_lds", "wait LDS / wave-cycle"),
+            ("valu_active", "VALU active / wave-cycle"), ("lds_active", "LDS active / wave-cycle")]
     lines = ["# rocprofv3 counters: %s" % title, "",
              "Commands (run from the repository root on one MI355X):", "", "```", command, "```", "",
-             "Per-kernel means per dispatch (counters summed over the device as rocprofv3 reports "
-             "them; GRBM_GUI_ACTIVE summed over the 8 XCDs; SQ_* cycle counters in quad-cycles "
-             "where the counter is defined so).", ""]
+             "Per library kernel, means per dispatch.  MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / "
+             "(GRBM_GUI_ACTIVE per XCD x 1024 SIMDs); FP64 MFMA TFLOP/s = "
+             "SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 / duration; the per-wave-cycle fractions are "
+             "SQ_WAIT_INST_ANY, SQ_WAIT_INST_LDS, SQ_ACTIVE_INST_VALU and SQ_ACTIVE_INST_LDS over "
+             "SQ_WAVE_CYCLES.", "",
+             "| kernel | dispatches | mean us | LDS bank conflicts | " +
+             " | ".join(h for _, h in cols) + " |",
+             "|---|---|---|---|" + "---|" * len(cols)]
+    out = {}
     for k, rec in tab.items():
-        lines.append("## %s" % k)
-        lines.append("")
-        lines.append("dispatches %d, mean duration %.1f us" % (rec.get("_n", 0), rec.get("_dur_us", 0.0)))
-        lines.append("")
-        lines.append("| counter | mean |")
-        lines.append("|---|---|")
-        for c in cols:
-            if c in rec:
-                lines.append("| %s | %.4g |" % (c, rec[c]))
-        for name, v in derived(rec).items():
-            lines.append("| %s (derived) | %.3f |" % (name, v))
-        lines.append("")
+        if not k.startswith("acex::"):
+            continue
+        d = derived(rec)
+        out[k] = d
+        vals = []
+        for key, _ in cols:
+            hit = [v for name, v in d.items() if name.startswith(key)]
+            vals.append("%.3f" % hit[0] if hit else "")
+        lines.append("| %s | %d | %.1f | %.3g | %s |" % (
+            k.replace("acex::", ""), rec.get("_n", 0), rec.get("_dur_us", 0.0),
+            rec.get("SQ_LDS_BANK_CONFLICT", 0.0), " | ".join(vals)))
+    lines.append("")
     with open(out_md, "w") as f:
         f.write("\n".join(lines))
-    return {k: derived(rec) for k, rec in tab.items()}
+    return out
 
 
 if __name__ == "__main__":
