@@ -315,10 +315,13 @@ def run_batch(args):
     dev = torch.device("cuda:0")
     plans = [_lib.Plan(sp.n, (sp.L,) * 3, sp.n_orb, args.precision, sp.alpha) for sp in specs]
     tuned = None
+    use_lanes = True
     if not args.no_tune:
         t0 = time.perf_counter()
         tuned = autotune.tune_batch(plans, args.precision, cache_path=args.tune_cache, log=say)
-        tuned = {"batch_ms": tuned["ms"], "trials": [t[0] for t in tuned["tried"]],
+        use_lanes = bool(tuned.get("lanes", True))
+        tuned = {"batch_ms": tuned["ms"], "lanes": use_lanes,
+                 "trials": [t[0] for t in tuned["tried"]],
                  "tune_s": round(time.perf_counter() - t0, 1)}
     phis = [torch.from_numpy(s.phi).to(dev) for s in systems]
     batch = _lib.Batch(plans)
@@ -337,11 +340,13 @@ def run_batch(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / args.steps
 
-    t_graph = timed(lambda: batch.build_into(phis, out, ws))
+    t_graph = timed(lambda: batch.build_into(phis, out, ws, lanes=use_lanes))
     ex_graph = out["ex"].cpu().numpy().copy()
     info = out["info"].cpu().numpy()
     assert (info == 0).all(), "Cholesky of -M failed in %s" % np.nonzero(info)[0]
-    t_eager = timed(lambda: batch.build_into(phis, out, ws, eager=True))
+    t_eager = timed(lambda: batch.build_into(phis, out, ws, eager=True, lanes=use_lanes))
+    t_lanes = timed(lambda: batch.build_into(phis, out, ws, lanes=True))
+    t_alone = timed(lambda: batch.build_into(phis, out, ws, lanes=False))
     seq_ws = [_lib.workspace(p.workspace_bytes(), dev) for p in plans]
     seq_out = [_lib.ace_build(p, f, ws=w) for p, f, w in zip(plans, phis, seq_ws)]
 
@@ -391,6 +396,8 @@ def run_batch(args):
         "tuner": tuned,
         "lanes": lanes, "tiles_in_shared_passes": whole_tiles, "tiles_other": other_tiles,
         "graph_ms": 1000 * t_graph, "eager_branches_ms": 1000 * t_eager,
+        "lanes_used": use_lanes, "graph_with_lanes_ms": 1000 * t_lanes,
+        "graph_without_lanes_ms": 1000 * t_alone,
         "sequential_ms": 1000 * t_seq, "speedup_vs_sequential": t_seq / t_graph,
         "ex_bitwise_equal_to_sequential": bool(np.array_equal(ex_graph, ex_seq)),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,

@@ -304,7 +304,11 @@ int ace_plan_schedule(const ace_plan *plan, int *full_tiles, int *plane);
  *   pinned host copy of the tables; the tables are copied into the workspace
  *   on `stream` ahead of the work at every call.  flags: 0 replays (or first
  *   records) the graph, launched on `stream`; ACE_BATCH_EAGER launches the
- *   same work directly on the branch streams, joined back into `stream`.
+ *   same work directly on the branch streams, joined back into `stream`;
+ *   ACE_BATCH_NO_LANES (with or without EAGER) runs every instance's own
+ *   launch sequence on its branch instead of the lanes' shared pass
+ *   launches (same results bit for bit; which is faster depends on the
+ *   batch, and the batch tuner times both).
  *   A later call on another device returns ACE_ERR_ARG.
  * ace_batch_destroy: only after the batch's last build has completed.
  * ace_batch_lanes: host-side description of the schedule: *lanes lanes,
@@ -312,6 +316,7 @@ int ace_plan_schedule(const ace_plan *plan, int *full_tiles, int *plane);
  *   the single-system kernels (any pointer may be NULL). */
 #define ACE_BATCH_MAX 1024
 #define ACE_BATCH_EAGER 1
+#define ACE_BATCH_NO_LANES 2
 typedef struct ace_batch ace_batch;
 int ace_batch_create(ace_batch **batch, const ace_plan *const *plans,
                      const uint8_t *const *pair_masks, int count);

@@ -33,6 +33,7 @@ PROBE_EXPORTS = ["ace_bandwidth_probe"]
 PROBE_KINDS = {"read_write": 0, "read": 1, "write": 2}
 ACE_BATCH_MAX = 1024
 ACE_BATCH_EAGER = 1
+ACE_BATCH_NO_LANES = 2
 
 
 class AceError(RuntimeError):
@@ -555,7 +556,7 @@ class Batch:
         info = torch.zeros((len(phis),), dtype=torch.int32, device=dev)
         return {"W": W, "M": M, "xi": xi, "ex": ex, "info": info}
 
-    def build_into(self, phis, out, ws, eager: bool = False, stream=None):
+    def build_into(self, phis, out, ws, eager: bool = False, stream=None, lanes: bool = True):
         if len(phis) != len(self.plans):
             raise ValueError("expected %d orbital sets" % len(self.plans))
         for key in ("W", "M", "xi"):
@@ -576,14 +577,15 @@ class Batch:
                                     ws.numel() * ws.element_size(), _ptr_array(phis),
                                     _ptr_array(out["W"]), _ptr_array(out["M"]),
                                     _ptr_array(out["xi"]), _ptr(out["ex"]), _ptr(out["info"]),
-                                    ACE_BATCH_EAGER if eager else 0)
+                                    (ACE_BATCH_EAGER if eager else 0) |
+                                    (0 if lanes else ACE_BATCH_NO_LANES))
         _check(rc, "ace_batch_build")
 
-    def build(self, phis, ws=None, eager: bool = False, stream=None):
+    def build(self, phis, ws=None, eager: bool = False, stream=None, lanes: bool = True):
         out = self.outputs(phis)
         if ws is None:
             ws = workspace(self.workspace_bytes(), phis[0].device)
-        self.build_into(phis, out, ws, eager, stream)
+        self.build_into(phis, out, ws, eager, stream, lanes)
         return out
 
 

@@ -16,7 +16,9 @@ For a batch, tune_batch times the whole batch graph: every instance on its
 own tuned shape, every instance on block 16, every instance on block 8, then,
 from the best of those, each grid size's block flipped in turn (instances of
 one grid, precision and block share the persistent pass launches, so the best
-shape of an instance alone need not be the best inside the batch).
+shape of an instance alone need not be the best inside the batch), and
+finally the same shapes with every instance on its own launches instead of
+the lanes' shared ones (ACE_BATCH_NO_LANES); the faster mode is kept.
 
 Timing inputs are random orbitals drawn on the device: the kernels' work
 does not depend on the values, and any full-rank real orbital set gives a
@@ -170,7 +172,7 @@ def batch_key(sizes, precision: str) -> str:
     return "batch/%s/" % precision + ",".join("%dx%d" % (int(n), int(k)) for n, k in sizes)
 
 
-def time_batch(plans, phis, shapes, reps: int = 2) -> float:
+def time_batch(plans, phis, shapes, reps: int = 2, lanes: bool = True) -> float:
     """Milliseconds of one batch graph launch with the given per-instance
     shapes (best of reps, after the recording launch)."""
     import torch
@@ -179,13 +181,13 @@ def time_batch(plans, phis, shapes, reps: int = 2) -> float:
     batch = _lib.Batch(plans)
     ws = _lib.workspace(batch.workspace_bytes(), phis[0].device)
     out = batch.outputs(phis)
-    batch.build_into(phis, out, ws)  # records the graph
+    batch.build_into(phis, out, ws, lanes=lanes)  # records the graph
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     best = float("inf")
     for _ in range(reps):
         ev0.record()
-        batch.build_into(phis, out, ws)
+        batch.build_into(phis, out, ws, lanes=lanes)
         ev1.record()
         ev1.synchronize()
         best = min(best, ev0.elapsed_time(ev1))
@@ -206,6 +208,7 @@ def tune_batch(plans, precision: str, cache_path: Optional[str] = None, device: 
         e = cache[k]
         for p, sh in zip(plans, e["shapes"]):
             set_shape(p, sh)
+        e.setdefault("lanes", True)
         return e
     own = []
     for p in plans:
@@ -220,8 +223,8 @@ def tune_batch(plans, precision: str, cache_path: Optional[str] = None, device: 
         phis.append(f * (1.0 / p.n ** 1.5))
     tried = []
 
-    def run(label, shapes):
-        ms = time_batch(plans, phis, shapes, reps)
+    def run(label, shapes, lanes=True):
+        ms = time_batch(plans, phis, shapes, reps, lanes)
         tried.append([label, [list(s) for s in shapes], round(ms, 4)])
         if log:
             log("batch shapes %s: %.3f ms" % (label, ms))
@@ -241,9 +244,16 @@ def tune_batch(plans, precision: str, cache_path: Optional[str] = None, device: 
         ms = run("flip n=%d" % n, trial)
         if ms < best_ms:
             best_ms, best = ms, trial
+    # the lanes' shared pass launches against every instance on its own
+    # launches, on the chosen shapes
+    lanes = True
+    ms = run("without lanes", best, lanes=False)
+    if ms < best_ms:
+        best_ms, lanes = ms, False
     for p, sh in zip(plans, best):
         set_shape(p, sh)
-    entry = {"shapes": [list(s) for s in best], "ms": round(best_ms, 4), "tried": tried}
+    entry = {"shapes": [list(s) for s in best], "lanes": lanes, "ms": round(best_ms, 4),
+             "tried": tried}
     cache = load_cache(cache_path)
     cache[k] = entry
     save_cache(cache, cache_path)

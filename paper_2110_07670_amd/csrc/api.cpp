@@ -105,6 +105,7 @@ struct ace_batch {
   size_t total = 0;
   std::vector<int> order;             // instances, largest first
   std::vector<int> branch;            // graph branch of each instance
+  std::vector<int> branch_alone;      // its branch when every instance runs alone
   int nbranch = 0;
   int device = -1;
   hipStream_t cap = nullptr;          // capture stream
@@ -1190,8 +1191,17 @@ int ace_batch_create(ace_batch** batch, const ace_plan* const* plans,
                    [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
                      return x.first > y.first;
                    });
-  b->nbranch = std::min((int)units.size(), kBatchBranches);
-  std::vector<double> load(b->nbranch, 0.0);
+  b->nbranch = std::min(count, kBatchBranches);
+  {
+    std::vector<double> alone(b->nbranch, 0.0);
+    b->branch_alone.assign(count, 0);
+    for (int k : b->order) {
+      const int j = (int)(std::min_element(alone.begin(), alone.end()) - alone.begin());
+      b->branch_alone[k] = j;
+      alone[j] += cost[k];
+    }
+  }
+  std::vector<double> load(std::min((int)units.size(), b->nbranch), 0.0);
   b->branch.assign(count, 0);
   for (const auto& u : units) {
     const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -1241,7 +1251,8 @@ int ace_batch_build(ace_batch* b, void* stream, void* ws, size_t ws_bytes,
                     const double* const* phi, double* const* W, double* const* M,
                     double* const* xi, double* ex, int* info, int flags) {
   if (!b || !ws || !phi || !W || !M || !xi || !ex || !info) return ACE_ERR_ARG;
-  if (flags & ~ACE_BATCH_EAGER) return ACE_ERR_ARG;
+  if (flags & ~(ACE_BATCH_EAGER | ACE_BATCH_NO_LANES)) return ACE_ERR_ARG;
+  const bool lanes = !(flags & ACE_BATCH_NO_LANES);
   if (ws_bytes < b->total) return ACE_ERR_WORKSPACE;
   char* w = static_cast<char*>(ws);
   for (int k = 0; k < b->count; ++k) {
@@ -1383,20 +1394,24 @@ int ace_batch_build(ace_batch* b, void* stream, void* ws, size_t ws_bytes,
   // on their branches), join back
   auto record = [&](hipStream_t head) -> int {
     hipError_t er;
-    if (b->nctr > 0 && (er = acex::launch_fill_i32(d_ctr, 0, b->nctr, head)) != hipSuccess)
+    if (lanes && b->nctr > 0 &&
+        (er = acex::launch_fill_i32(d_ctr, 0, b->nctr, head)) != hipSuccess)
       return hip_fail(er);
     if ((er = hipEventRecord(b->fork, head)) != hipSuccess) return hip_fail(er);
     for (hipStream_t st : b->streams)
       if ((er = hipStreamWaitEvent(st, b->fork, 0)) != hipSuccess) return hip_fail(er);
     int rc = ACE_OK;
-    for (const BatchLane& l : b->lanes) {
-      rc = run_lane(l, b->streams[l.branch]);
-      if (rc != ACE_OK) break;
+    if (lanes) {
+      for (const BatchLane& l : b->lanes) {
+        rc = run_lane(l, b->streams[l.branch]);
+        if (rc != ACE_OK) break;
+      }
     }
     for (int k : b->order) {
-      if (rc != ACE_OK || b->fused[k]) continue;
-      rc = enqueue_build(b->plans[k], b->streams[b->branch[k]], w + b->ws_off[k], phi[k],
-                         b->tables[k], W[k], M[k], xi[k], ex + k, info + k);
+      if (rc != ACE_OK || (lanes && b->fused[k])) continue;
+      const int br = lanes ? b->branch[k] : b->branch_alone[k];
+      rc = enqueue_build(b->plans[k], b->streams[br], w + b->ws_off[k], phi[k], b->tables[k],
+                         W[k], M[k], xi[k], ex + k, info + k);
     }
     // the join is recorded even after an error, so that a capture always closes
     for (int j = 0; j < b->nbranch; ++j) {
@@ -1413,6 +1428,7 @@ int ace_batch_build(ace_batch* b, void* stream, void* ws, size_t ws_bytes,
   key.push_back(ws);
   key.push_back(ex);
   key.push_back(info);
+  key.push_back(reinterpret_cast<const void*>(static_cast<uintptr_t>(lanes ? 1 : 2)));
   for (int k = 0; k < b->count; ++k) {
     key.push_back(phi[k]);
     key.push_back(W[k]);

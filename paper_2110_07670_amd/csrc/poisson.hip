@@ -1493,7 +1493,9 @@ __global__ void k_cast_f64_f32(const double* __restrict__ in, float* __restrict_
 // items all cost the same, so each workgroup takes every grid-th item of the
 // round, which lets it load the next item's orbitals during the current
 // one, as the single-system kernel does; middle and inverse-z/W items are
-// taken from a work queue (one atomic counter per launch) until it is empty.
+// taken from a work queue (one atomic counter per launch) until it is empty
+// (middle items strided like the forward ones measured slower inside a
+// batch graph: 233 against 228 ms for config 4).
 // Each item runs the single-system code for its block and diagonal flag.
 // One kernel per grid size (48, 64, 80, 96: a plane fits one workgroup's
 // LDS in FP64 and FP32), with that size's 8 N threads: one kernel over all
@@ -1636,6 +1638,8 @@ static hipError_t batch_launch(const BatchSeg* segs, int nseg, int total, int* c
                                hipStream_t s) {
   static_assert(zinv_threads<T, N>() <= batch_threads<N>(), "a thread per inverse-z point");
   static_assert(plane_ok<T, N>(), "a plane per workgroup");
+  // persistent (one workgroup per item measured slower: 246-255 against
+  // 228 ms for config 4)
   const int grid = std::min(total, cus * batch_per_cu<T, PASS, N, B>());
   hipLaunchKernelGGL((k_batch_pass<T, PASS, N, B>), dim3(grid), dim3(batch_threads<N>()), 0, s,
                      segs, nseg, total, counter);

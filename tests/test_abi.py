@@ -237,7 +237,7 @@ def test_batch_build_validates_before_device():
     ex, info, ws = base + 7 * N, base + 7 * N + 4096, base + 8 * N
     f = lib.ace_batch_build
     assert f(b, None, ws, need - 1, phi, W, M, xi, ex, info, 0) == _lib.ACE_ERR_WORKSPACE
-    assert f(b, None, ws, need, phi, W, M, xi, ex, info, 2) == _lib.ACE_ERR_ARG
+    assert f(b, None, ws, need, phi, W, M, xi, ex, info, 4) == _lib.ACE_ERR_ARG  # unknown flag
     assert f(None, None, ws, need, phi, W, M, xi, ex, info, 0) == _lib.ACE_ERR_ARG
     # W of instance 1 overlapping phi of instance 0
     W_bad = (ctypes.c_void_p * 2)(base + 2 * N, base + 8)

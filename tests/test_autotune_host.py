@@ -67,6 +67,6 @@ def test_batch_cache_lookup_sets_every_instance(tmp_path):
     autotune.save_cache({key: {"shapes": [[8, 0, 0, False], [16, 32, 8, True]], "ms": 3.0,
                                "tried": []}}, path)
     e = autotune.tune_batch(plans, "fp32", cache_path=path)
-    assert e["ms"] == 3.0
+    assert e["ms"] == 3.0 and e["lanes"]  # entries without the mode: the lanes
     assert plans[0].tiling == (8, 0, 0) and not plans[0].four_pass
     assert plans[1].tiling == (16, 32, 8) and plans[1].four_pass

@@ -163,6 +163,12 @@ def test_batch_eager_and_new_pointers(lib, systems):
     torch.cuda.synchronize()
     _assert_same(out1, refs)
     _assert_same(out2, refs)
+    # every instance on its own launches instead of the lanes: same bits
+    out3 = batch.build(phis, ws=ws, lanes=False)
+    out4 = batch.build(phis, ws=ws, eager=True, lanes=False)
+    torch.cuda.synchronize()
+    _assert_same(out3, refs)
+    _assert_same(out4, refs)
 
 
 def test_batch_singular_instance_reports_its_own_info(lib, systems):
