@@ -1638,8 +1638,9 @@ static hipError_t batch_launch(const BatchSeg* segs, int nseg, int total, int* c
                                hipStream_t s) {
   static_assert(zinv_threads<T, N>() <= batch_threads<N>(), "a thread per inverse-z point");
   static_assert(plane_ok<T, N>(), "a plane per workgroup");
-  // persistent (one workgroup per item measured slower: 246-255 against
-  // 228 ms for config 4)
+  // persistent, the whole chip (one workgroup per item measured slower,
+  // 246-255 against 228 ms for config 4, and so did half or a quarter of
+  // the chip per launch, 249 and 383 ms)
   const int grid = std::min(total, cus * batch_per_cu<T, PASS, N, B>());
   hipLaunchKernelGGL((k_batch_pass<T, PASS, N, B>), dim3(grid), dim3(batch_threads<N>()), 0, s,
                      segs, nseg, total, counter);
