@@ -84,3 +84,33 @@ def test_config3_fp32_bulk_errors(setup):
     assert r["M_err"] < 1e-5
     assert r["W_row_err"] < 1e-5
     assert r["ace_row_err"] < 1e-5
+
+
+def test_config3_fp64_full_arrays_across_schedules(setup):
+    """Every element of W, M and xi of the benchmarked FP64 build (slab
+    three-pass schedule, block 8) against the four-pass build with block 16,
+    whose kernels and pair packing are different (and oracle-checked element
+    by element on smaller grids); E_x against the oracle for both."""
+    import torch
+    spec, s, ref, row, w_ref, lib = setup
+    _say("config3 fp64 full arrays: slab three-pass block 8 vs four-pass block 16")
+    phi = torch.from_numpy(s.phi).to("cuda:0")
+    p3 = lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, "fp64", spec.alpha)
+    assert p3.schedule() == ("three_pass", False) and p3.tiling[0] == 8
+    a = lib.ace_build(p3, phi)
+    torch.cuda.synchronize()
+    A = {k: a[k].cpu().numpy() for k in ("W", "M", "xi", "ex")}
+    del a
+    p4 = lib.Plan(spec.n, (spec.L,) * 3, spec.n_orb, "fp64", spec.alpha)
+    p4.set_tiling(16)
+    p4.set_schedule(True)
+    b = lib.ace_build(p4, phi)
+    torch.cuda.synchronize()
+    for key in ("W", "M", "xi"):
+        x, y = A[key], b[key].cpu().numpy()
+        norm = O.rel_err(x, y)
+        elem = float(np.abs(x - y).max() / np.abs(y).max())
+        print("config3 fp64 %s: normwise %.2e, elementwise %.2e" % (key, norm, elem), flush=True)
+        assert norm < 1e-12 and elem < 1e-11, key
+    for ex in (float(A["ex"][0]), float(b["ex"].item())):
+        assert abs(ex - ref["ex"]) < 1e-10 * abs(ref["ex"])
