@@ -51,10 +51,13 @@ bool three_pass_ok(int n, int prec, int block);
 bool fused_rows_ok(int n, int prec, int block);
 hipError_t launch_inv_y(const GridArgs& g, void* S, int npack, hipStream_t s);
 hipError_t launch_mid(const GridArgs& g, void* S, int npack, hipStream_t s);
-// phi: the orbitals in the bulk precision (FP64, or the FP32 copy).
+// phi: the orbitals in the bulk precision (FP64, or the FP32 copy).  With
+// S2 (and orbs2) one launch also does a second tile of the same kind whose
+// orbital blocks are disjoint from the first's.
 hipError_t launch_zinv_acc(const GridArgs& g, int block, bool diag, const void* S,
                            const void* phi, double* W, const int* orbs, double alpha,
-                           hipStream_t s);
+                           hipStream_t s, const void* S2 = nullptr,
+                           const int* orbs2 = nullptr);
 // x transforms with the Coulomb multiply between forward and inverse, in place.
 hipError_t launch_poisson_x(const GridArgs& g, void* S, int npack, hipStream_t s);
 // x forward transform and sum of K |Z|^2 per workgroup into part[npack][parts_per_pack].

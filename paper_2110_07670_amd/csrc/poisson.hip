@@ -820,14 +820,22 @@ __device__ __forceinline__ void zinv_item(const cx<T>* __restrict__ S,
   }
 }
 
+// One launch may serve two tiles with disjoint orbital blocks (their W rows
+// differ): workgroups nb and up take the second tile's scratch S2 and
+// orbitals orbs2 (nb, the workgroups of one tile, is a multiple of 8, so
+// every workgroup keeps its XCD order).  Two tiles' 2 nb workgroups fill
+// whole rounds of the chip where one tile's leave the last round half empty.
 template <typename T, int N, int B, bool DIAG, bool ROWS>
 __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
     const cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, const T* __restrict__ phi,
-    double* __restrict__ W, const int* __restrict__ orbs, double alpha, int64_t npts) {
+    double* __restrict__ W, const int* __restrict__ orbs, double alpha, int64_t npts,
+    const cx<T>* __restrict__ S2, const int* __restrict__ orbs2, int nb) {
   __shared__ cx<T> lds[(B / 2) * zinv_rows<T, N, ROWS>() * (N + 1)];
   __shared__ cx<T> stw[N];
-  zinv_item<T, N, B, DIAG, ROWS, zinv_threads<T, N, ROWS>()>(S, tw, phi, W, orbs, alpha, npts,
-                                                               blockIdx.x, lds, stw);
+  const int second = (int)blockIdx.x >= nb;
+  zinv_item<T, N, B, DIAG, ROWS, zinv_threads<T, N, ROWS>()>(
+      second ? S2 : S, tw, phi, W, second ? orbs2 : orbs, alpha, npts,
+      (int)blockIdx.x - (second ? nb : 0), lds, stw);
 }
 
 // ------------------------------------------------------------------ y/z slabs, forward
@@ -1799,17 +1807,22 @@ static hipError_t mid_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
 
 template <typename T, int N, int B, bool ROWS>
 static hipError_t zinv_launch(const GridArgs& g, bool diag, const void* S, const void* phi,
-                              double* W, const int* orbs, double alpha, hipStream_t s) {
+                              double* W, const int* orbs, double alpha, hipStream_t s,
+                              const void* S2, const int* orbs2) {
   if constexpr (zinv_ok<T, N, B, ROWS>()) {
-    const dim3 grid(N * (N / zinv_rows<T, N, ROWS>())), block(zinv_threads<T, N, ROWS>());
+    const int nb = N * (N / zinv_rows<T, N, ROWS>());
+    static_assert((N * (N / zinv_rows<T, N, ROWS>())) % 8 == 0, "whole XCD groups per tile");
+    const dim3 grid(S2 ? 2 * nb : nb), block(zinv_threads<T, N, ROWS>());
+    const cx<T>* s2 = static_cast<const cx<T>*>(S2 ? S2 : S);
+    const int* o2 = S2 ? orbs2 : orbs;
     if (diag)
       hipLaunchKernelGGL((k_zinv_acc<T, N, B, true, ROWS>), grid, block, 0, s,
                          static_cast<const cx<T>*>(S), static_cast<const cx<T>*>(g.tw),
-                         static_cast<const T*>(phi), W, orbs, alpha, g.npts);
+                         static_cast<const T*>(phi), W, orbs, alpha, g.npts, s2, o2, nb);
     else
       hipLaunchKernelGGL((k_zinv_acc<T, N, B, false, ROWS>), grid, block, 0, s,
                          static_cast<const cx<T>*>(S), static_cast<const cx<T>*>(g.tw),
-                         static_cast<const T*>(phi), W, orbs, alpha, g.npts);
+                         static_cast<const T*>(phi), W, orbs, alpha, g.npts, s2, o2, nb);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
@@ -1817,11 +1830,12 @@ static hipError_t zinv_launch(const GridArgs& g, bool diag, const void* S, const
 
 template <typename T, int N, int B>
 static hipError_t zinv_t(const GridArgs& g, bool diag, const void* S, const void* phi,
-                         double* W, const int* orbs, double alpha, hipStream_t s) {
+                         double* W, const int* orbs, double alpha, hipStream_t s,
+                         const void* S2, const int* orbs2) {
   if constexpr (zinv_ok<T, N, B, false>())
-    return zinv_launch<T, N, B, false>(g, diag, S, phi, W, orbs, alpha, s);
+    return zinv_launch<T, N, B, false>(g, diag, S, phi, W, orbs, alpha, s, S2, orbs2);
   else
-    return zinv_launch<T, N, B, true>(g, diag, S, phi, W, orbs, alpha, s);
+    return zinv_launch<T, N, B, true>(g, diag, S, phi, W, orbs, alpha, s, S2, orbs2);
 }
 
 // the large-grid schedule's inverse y lines (its inverse z is fused with W)
@@ -1942,16 +1956,16 @@ hipError_t launch_mid(const GridArgs& g, void* S, int npack, hipStream_t s) {
 
 hipError_t launch_zinv_acc(const GridArgs& g, int block, bool diag, const void* S,
                            const void* phi, double* W, const int* orbs, double alpha,
-                           hipStream_t s) {
+                           hipStream_t s, const void* S2, const int* orbs2) {
   switch (g.n) {
-#define X(N)                                                                               \
-  case N:                                                                                  \
-    if (block == 16)                                                                       \
-      return g.prec == 0 ? zinv_t<double, N, 16>(g, diag, S, phi, W, orbs, alpha, s)       \
-                         : zinv_t<float, N, 16>(g, diag, S, phi, W, orbs, alpha, s);       \
-    if (block == 8)                                                                        \
-      return g.prec == 0 ? zinv_t<double, N, 8>(g, diag, S, phi, W, orbs, alpha, s)        \
-                         : zinv_t<float, N, 8>(g, diag, S, phi, W, orbs, alpha, s);        \
+#define X(N)                                                                                 \
+  case N:                                                                                    \
+    if (block == 16)                                                                         \
+      return g.prec == 0 ? zinv_t<double, N, 16>(g, diag, S, phi, W, orbs, alpha, s, S2, orbs2) \
+                         : zinv_t<float, N, 16>(g, diag, S, phi, W, orbs, alpha, s, S2, orbs2); \
+    if (block == 8)                                                                          \
+      return g.prec == 0 ? zinv_t<double, N, 8>(g, diag, S, phi, W, orbs, alpha, s, S2, orbs2)  \
+                         : zinv_t<float, N, 8>(g, diag, S, phi, W, orbs, alpha, s, S2, orbs2);  \
     return hipErrorInvalidValue;
     ACEX_SIZES(X)
 #undef X
