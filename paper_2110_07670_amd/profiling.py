@@ -7,7 +7,7 @@ counters read for a known streaming pass in the same process
 (bench.py --copy-calibration: one in-place read + write launch over 1 GiB,
 k_probe_rw, whose true traffic is 1 GiB read + 1 GiB written).
 
-Usage: python -m paper_2110_07670_amd.profiling TRACE_DB FETCH_DB WRITE_DB OUT.md "COMMAND"
+Usage: python -m paper_2110_07670_amd.profiling TRACE_DB FETCH_DB WRITE_DB OUT.md "COMMAND" ["TITLE"]
        python -m paper_2110_07670_amd.profiling --trace-only TRACE_DB OUT.md "TITLE" "COMMAND"
        python -m paper_2110_07670_amd.profiling --counters OUT.md "TITLE" "COMMAND" DB [DB ...]
 (the second form: kernel times per kernel and per stage from a trace alone;
@@ -92,7 +92,10 @@ def calibration(fetch, write):
     return true_kib / cf[0][1], true_kib / cw[0][1]
 
 
-def summarize(trace_db, fetch_db, write_db, out_md, command):
+DEFAULT_TITLE = "ACE build, water32_n96 (128 orbitals, 96^3, FP64)"
+
+
+def summarize(trace_db, fetch_db, write_db, out_md, command, title=DEFAULT_TITLE):
     stats = kernel_stats(trace_db)
     fetch = counters(fetch_db, "FETCH_SIZE")
     write = counters(write_db, "WRITE_SIZE")
@@ -103,7 +106,7 @@ def summarize(trace_db, fetch_db, write_db, out_md, command):
     for _, k, v, _ in write:
         per[k]["write"].append(v)
     stage_bytes = collections.defaultdict(list)
-    lines = ["# rocprofv3 summary: ACE build, water32_n96 (128 orbitals, 96^3, FP64)", "",
+    lines = ["# rocprofv3 summary: %s" % title, "",
              "Commands (run from the repository root on one MI355X):", "", "```", command, "```", "",
              "Counter calibration (one in-place read + write launch over 1 GiB in the same "
              "process, %s): FETCH_SIZE x %.3f, WRITE_SIZE x %.3f give true bytes."
@@ -246,7 +249,7 @@ if __name__ == "__main__":
                          indent=1))
     elif len(sys.argv) == 6 and sys.argv[1] == "--trace-only":
         print(json.dumps(summarize_trace(*sys.argv[2:6]), indent=1))
-    elif len(sys.argv) == 6:
-        print(json.dumps(summarize(*sys.argv[1:6]), indent=1))
+    elif len(sys.argv) in (6, 7):
+        print(json.dumps(summarize(*sys.argv[1:]), indent=1))
     else:
         sys.exit(__doc__)
