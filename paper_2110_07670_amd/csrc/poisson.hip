@@ -545,10 +545,14 @@ constexpr bool slab_ok() { return !plane_ok<T, N>() && slab_count<T, N>() > 0; }
 // the outputs of its first slab go to LDS, those of the others wait in
 // registers (at most 72 per thread with 512 FP64 threads, 48 with 768, 32
 // with 1024 FP32 threads: beyond that the kernels spill).  The first step is
-// recomputed SL / SPW times per plane.
-template <typename T, int SPW, int SL>
+// recomputed SL / SPW times per plane.  On grids whose plane fits LDS (the
+// two-slab forward pass below) FP32 workgroups have 512 threads too, so that
+// two of them share a CU.
+template <typename T, int N, int SPW>
 constexpr int slab_threads() {
-  return sizeof(T) == 4 ? 1024 : (SPW == SL ? 512 : 768);
+  constexpr int SL = slab_count<T, N>();
+  if constexpr (sizeof(T) == 4) return plane_ok<T, N>() ? 512 : 1024;
+  else return SPW == SL ? 512 : 768;
 }
 
 template <typename T, int N>
@@ -569,6 +573,25 @@ constexpr int slab_spw() {
 template <typename T, int N>
 constexpr bool slab3_ok() {
   return slab_ok<T, N>() && slab_spw<T, N>() == slab_count<T, N>();
+}
+
+// Plane-fitting grids whose plane workgroup takes more than half of a CU's
+// LDS (FP64 80^3 and 96^3, FP32 120^3 and 128^3) also run the three-pass
+// forward pass as two slabs: one 512-thread workgroup per plane takes both
+// slabs from one first step, holding the second slab's first-step outputs
+// in registers, and two such workgroups share a CU, so that one's transform
+// steps overlap the other's loads and stores.  (A plane workgroup's waves
+// all move through the same phase between barriers, so its memory traffic
+// barely overlaps its arithmetic.)  Measured, one 128-transform launch
+// against the plane kernel (with its FP32 prefetch one step later than now):
+// FP64 96^3 551 against 606 us, 80^3 333 against 381; FP32 128^3 752 against
+// 864, 120^3 734 against 967; per build, the forward pass of the 96^3 FP64
+// build of 128 orbitals 17.4 -> 16.1 ms, of the 128^3 FP32 build of 256
+// orbitals 105 -> 101 ms.
+template <typename T, int N>
+constexpr bool fwd_slabs() {
+  return plane_ok<T, N>() && slab_count<T, N>() == 2 &&
+         2 * (((long)N * (N + 1) + N) * (long)sizeof(cx<T>) + 64) > kLdsBytes;
 }
 
 // Rows of y per inverse-z workgroup (one workgroup: rows x N points).  Eight
@@ -862,13 +885,13 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
 // ZXY: write S[kz][x][ky] (the large-grid three-pass schedule) instead of
 // S[x][ky][kz], through LDS so that the stores run along ky.
 template <typename T, int N, int SPW, bool ZXY>
-__global__ __launch_bounds__((slab_threads<T, SPW, slab_count<T, N>()>())) void k_slab_fwd(
+__global__ __launch_bounds__((slab_threads<T, N, SPW>())) void k_slab_fwd(
     const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
     cx<T>* __restrict__ S, int npack, int64_t npts) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2;
   constexpr int SL = slab_count<T, N>(), ZC = N / SL, K1S = ZC / N2, PZ = ZC + 1;
   constexpr int NG = SL / SPW;                          // workgroups per plane
-  constexpr int NT = slab_threads<T, SPW, SL>();
+  constexpr int NT = slab_threads<T, N, SPW>();
   constexpr int Q = (N * N2 + NT - 1) / NT;            // first-step tasks per thread
   constexpr int KH = SPW > 1 ? (SPW - 1) * K1S : 1;    // outputs held per task
   static_assert(SL > 0 && ZC % N2 == 0 && SL % SPW == 0, "whole second-step blocks per slab");
@@ -1007,12 +1030,12 @@ __global__ __launch_bounds__((slab_threads<T, SPW, slab_count<T, N>()>())) void 
 // pass is then the plane-fitting grids' one.
 
 template <typename T, int N>
-__global__ __launch_bounds__((slab_threads<T, slab_count<T, N>(), slab_count<T, N>()>())) void
+__global__ __launch_bounds__((slab_threads<T, N, slab_count<T, N>()>())) void
 k_slab_mid(cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts, T g0,
            T g1, T g2, T kscale) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2;
   constexpr int SL = slab_count<T, N>(), ZC = N / SL, K1S = ZC / N2, PZ = ZC + 1;
-  constexpr int NT = slab_threads<T, SL, SL>();
+  constexpr int NT = slab_threads<T, N, SL>();
   constexpr int Q = (N * N2 + NT - 1) / NT;   // final-step tasks (x, t2) per thread
   constexpr int KH = (SL - 1) * K1S;          // values held per task
   __shared__ cx<T> lds[N * PZ];
@@ -1620,16 +1643,22 @@ __attribute__((amdgpu_waves_per_eu(batch_waves<T, PASS, N, B>()))) void k_batch_
   }
 }
 
+// The forward items do whole planes (the plane kernel's arithmetic): grids
+// whose own forward pass takes the two-slab form stay on their own launches,
+// so that every result is bitwise the system's own build.
 bool batch_ok(int n, int prec, int block) {
   if (block != 8 && block != 16) return false;
+  bool slabs = false;
   switch (n) {
-#define X(NN) case NN:
+#define X(NN)                                                               \
+  case NN:                                                                  \
+    slabs = prec == 0 ? fwd_slabs<double, NN>() : fwd_slabs<float, NN>(); \
+    break;
     ACEX_BATCH_SIZES(X)
 #undef X
-    break;
     default: return false;
   }
-  return three_pass_ok(n, prec, block);
+  return !slabs && three_pass_ok(n, prec, block);
 }
 
 int batch_items(int pass, int n, int npack) {
@@ -1744,6 +1773,14 @@ template <typename T, int N>
 static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs, int npack,
                            void* S, bool zxy, hipStream_t s) {
   const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
+  if constexpr (fwd_slabs<T, N>()) {
+    if (zxy) {
+      hipLaunchKernelGGL((k_slab_fwd<T, N, 2, true>), dim3(N * npack),
+                         dim3(slab_threads<T, N, 2>()), 0, s, static_cast<const T*>(phi), packs,
+                         tw, static_cast<cx<T>*>(S), npack, g.npts);
+      return hipGetLastError();
+    }
+  }
   if constexpr (plane_ok<T, N>()) {
     const int items = N * npack;
     const int grid = items < g.cus ? ((items + 7) / 8) * 8 : g.cus;
@@ -1760,13 +1797,13 @@ static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs
     if (zxy) {
       if constexpr (slab3_ok<T, N>())
         hipLaunchKernelGGL((k_slab_fwd<T, N, SPW, true>), dim3(N * npack * (SL / SPW)),
-                           dim3(slab_threads<T, SPW, SL>()), 0, s, static_cast<const T*>(phi),
+                           dim3(slab_threads<T, N, SPW>()), 0, s, static_cast<const T*>(phi),
                            packs, tw, static_cast<cx<T>*>(S), npack, g.npts);
       else
         return hipErrorInvalidValue;
     } else {
       hipLaunchKernelGGL((k_slab_fwd<T, N, SPW, false>), dim3(N * npack * (SL / SPW)),
-                         dim3(slab_threads<T, SPW, SL>()), 0, s, static_cast<const T*>(phi),
+                         dim3(slab_threads<T, N, SPW>()), 0, s, static_cast<const T*>(phi),
                          packs, tw, static_cast<cx<T>*>(S), npack, g.npts);
     }
   } else {
@@ -1808,7 +1845,7 @@ static hipError_t mid_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
     return hipGetLastError();
   } else if constexpr (slab3_ok<T, N>()) {
     constexpr int SL = slab_count<T, N>();
-    hipLaunchKernelGGL((k_slab_mid<T, N>), dim3(N * npack), dim3(slab_threads<T, SL, SL>()), 0,
+    hipLaunchKernelGGL((k_slab_mid<T, N>), dim3(N * npack), dim3(slab_threads<T, N, SL>()), 0,
                        s, static_cast<cx<T>*>(S), static_cast<const cx<T>*>(g.tw), npack, g.npts,
                        T(g.g2[0]), T(g.g2[1]), T(g.g2[2]), T(g.kscale));
     return hipGetLastError();
