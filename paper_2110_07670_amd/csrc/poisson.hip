@@ -136,9 +136,10 @@ __device__ __forceinline__ T coulomb_k(int kx, int ky, int kz, T g0, T g1, T g2,
 
 // ------------------------------------------------------------------ y/z plane, forward
 // Persistent: each workgroup walks items (x, pack) with a stride of the grid
-// size.  The orbital values of the next item are loaded into registers while
-// the current item is transformed, so their latency hides behind its last
-// steps and its stores (one such workgroup fills a CU's LDS, so there is no
+// size, as many workgroups per CU as are resident at once.  The orbital
+// values of the next item are loaded into registers while the current item
+// is transformed, so their latency hides behind its last steps and its
+// stores (on the larger grids one such workgroup fills a CU, so there is no
 // second workgroup to overlap with): FP32 ones once the z transform is done,
 // FP64 ones after the first y step (measured per precision: issued after the
 // z transform, FP32 passes take 8% (96^3) and 10% (128^3) less time, the FP64
@@ -1769,6 +1770,24 @@ int energy_parts_per_pack(int n) {
   }
 }
 
+// Forward plane workgroups resident per CU (registers and LDS permitting,
+// up to three on the small grids): the persistent grid is that many per CU.
+// One launch of 128 transforms, one against two or three per CU: FP32 48^3
+// 83 -> 59 us, 64^3 92 -> 61 us; FP64 48^3 83 -> 66 us, 64^3 151 -> 123 us.
+template <typename T, int N, bool ZXY>
+static int fwd_per_cu() {
+  static std::atomic<int> cached{0};
+  const int v = cached.load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_plane_fwd<T, N, ZXY>,
+                                                   fwd_threads<N>(), 0) != hipSuccess ||
+      occ < 1)
+    occ = 1;
+  cached.store(occ, std::memory_order_relaxed);
+  return occ;
+}
+
 template <typename T, int N>
 static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs, int npack,
                            void* S, bool zxy, hipStream_t s) {
@@ -1783,7 +1802,8 @@ static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs
   }
   if constexpr (plane_ok<T, N>()) {
     const int items = N * npack;
-    const int grid = items < g.cus ? ((items + 7) / 8) * 8 : g.cus;
+    const int cap = g.cus * (zxy ? fwd_per_cu<T, N, true>() : fwd_per_cu<T, N, false>());
+    const int grid = items < cap ? ((items + 7) / 8) * 8 : cap;
     if (zxy)
       hipLaunchKernelGGL((k_plane_fwd<T, N, true>), dim3(grid), dim3(fwd_threads<N>()), 0, s,
                          static_cast<const T*>(phi), packs, tw, static_cast<cx<T>*>(S), npack,
