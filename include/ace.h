@@ -254,9 +254,8 @@ int ace_plan_tiling(const ace_plan *plan, int *block, int *chunk, int *pencils);
 /* Transform schedule.  ACE_SCHEDULE_AUTO: full pair tiles (block x block
  * orbitals, every pair kept; block 8 or 16) take three passes over the
  * scratch grids where the grid's plane fits a workgroup's LDS (FP64 n <= 96,
- * FP32 n <= 128; where a plane takes more than half of it, FP64 80^3 and
- * 96^3 and FP32 120^3 and 128^3, the forward pass takes each plane two slabs
- * at a time so that two workgroups share a compute unit), or where a
+ * FP32 n <= 128; from 48^3 up the forward pass takes each plane two slabs
+ * at a time so that several workgroups share a compute unit), or where a
  * workgroup can take a plane slab by slab (FP64 120^3 and 128^3, block 8),
  * and four elsewhere; in all of these the
  * inverse z transform feeds the W update directly.  Every other tile takes
@@ -283,10 +282,9 @@ int ace_plan_schedule(const ace_plan *plan, int *full_tiles, int *plane);
  * One ace_build per instance (each with its own plan, launch shapes and
  * optional pair mask), recorded once into a HIP graph; later calls with the
  * same pointers replay the recorded graph.  Instances with the same grid
- * (48, 64, 80 or 96 points per axis in FP32, 48 or 64 in FP64, whose
- * forward pass at 80^3 and 96^3 works two slabs at a time), bulk precision
- * and the automatic schedule form a lane: round r of a lane takes tile r of
- * each of its instances, every whole three-pass tile of the round in one persistent
+ * (48, 64, 80 or 96 points per axis), bulk precision and the automatic
+ * schedule form a lane: round r of a lane takes tile r of each of its
+ * instances, every whole three-pass tile of the round in one persistent
  * launch per pass (workgroups draining a shared work queue of the
  * instances' transform planes and point blocks), the lane's other tiles
  * after them.  Lanes and the remaining instances run concurrently on the

@@ -576,23 +576,23 @@ constexpr bool slab3_ok() {
   return slab_ok<T, N>() && slab_spw<T, N>() == slab_count<T, N>();
 }
 
-// Plane-fitting grids whose plane workgroup takes more than half of a CU's
-// LDS (FP64 80^3 and 96^3, FP32 120^3 and 128^3) also run the three-pass
-// forward pass as two slabs: one 512-thread workgroup per plane takes both
-// slabs from one first step, holding the second slab's first-step outputs
-// in registers, and two such workgroups share a CU, so that one's transform
-// steps overlap the other's loads and stores.  (A plane workgroup's waves
-// all move through the same phase between barriers, so its memory traffic
-// barely overlaps its arithmetic.)  Measured, one 128-transform launch
-// against the plane kernel (with its FP32 prefetch one step later than now):
-// FP64 96^3 551 against 606 us, 80^3 333 against 381; FP32 128^3 752 against
-// 864, 120^3 734 against 967; per build, the forward pass of the 96^3 FP64
+// Plane-fitting grids from 48^3 up also run the three-pass forward pass as
+// two slabs: one 512-thread workgroup per plane takes both slabs from one
+// first step, holding the second slab's first-step outputs in registers;
+// half a plane of LDS lets two or more such workgroups share a CU, so that
+// one's transform steps overlap another's loads and stores.  (A plane
+// workgroup's waves all move through the same phase between barriers, so
+// its memory traffic barely overlaps its arithmetic, and the large planes
+// leave room for one per CU.)  Measured, one 128-transform launch, slabs
+// against planes: FP64 96^3 551 / 606 us, 80^3 333 / 381, 64^3 118 / 125,
+// 48^3 58 / 71; FP32 128^3 752 / 864, 120^3 734 / 967 (both with the plane
+// kernel's earlier FP32 prefetch placement), 96^3 300 / 341, 80^3 122 / 198,
+// 64^3 62 / 65, 48^3 52 / 57.  Per build, the forward pass of the 96^3 FP64
 // build of 128 orbitals 17.4 -> 16.1 ms, of the 128^3 FP32 build of 256
 // orbitals 105 -> 101 ms.
 template <typename T, int N>
 constexpr bool fwd_slabs() {
-  return plane_ok<T, N>() && slab_count<T, N>() == 2 &&
-         2 * (((long)N * (N + 1) + N) * (long)sizeof(cx<T>) + 64) > kLdsBytes;
+  return plane_ok<T, N>() && N >= 48 && slab_count<T, N>() == 2;
 }
 
 // Rows of y per inverse-z workgroup (one workgroup: rows x N points).  Eight
@@ -885,36 +885,31 @@ __global__ __launch_bounds__((zinv_threads<T, N, ROWS>())) void k_zinv_acc(
 
 // ZXY: write S[kz][x][ky] (the large-grid three-pass schedule) instead of
 // S[x][ky][kz], through LDS so that the stores run along ky.
-template <typename T, int N, int SPW, bool ZXY>
-__global__ __launch_bounds__((slab_threads<T, N, SPW>())) void k_slab_fwd(
-    const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
-    cx<T>* __restrict__ S, int npack, int64_t npts) {
+// The work of one slab workgroup of NT threads on plane x of one transform
+// (pack pk, scratch grid Sp), slab group grp: lds holds N (ZC + 1) values,
+// stw the N four-step twiddles, filled (and a barrier passed) before the
+// call.  The slab kernel runs one item per workgroup; the batch forward
+// items on the grids that take the two-slab form run the same function
+// with the same thread count, so their results are bitwise the same.  The
+// caller puts a barrier between two calls (the last step reads LDS).
+template <typename T, int N, int SPW, bool ZXY, int NT>
+__device__ __forceinline__ void slab_fwd_item(const T* __restrict__ phi, const Pack pk,
+                                              cx<T>* __restrict__ Sp, int x, int grp,
+                                              int64_t npts, cx<T>* __restrict__ lds,
+                                              const cx<T>* __restrict__ stw) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2;
   constexpr int SL = slab_count<T, N>(), ZC = N / SL, K1S = ZC / N2, PZ = ZC + 1;
   constexpr int NG = SL / SPW;                          // workgroups per plane
-  constexpr int NT = slab_threads<T, N, SPW>();
   constexpr int Q = (N * N2 + NT - 1) / NT;            // first-step tasks per thread
   constexpr int KH = SPW > 1 ? (SPW - 1) * K1S : 1;    // outputs held per task
   static_assert(SL > 0 && ZC % N2 == 0 && SL % SPW == 0, "whole second-step blocks per slab");
-  __shared__ cx<T> lds[N * PZ];
-  __shared__ cx<T> stw[N];
-  // item: (x, transform, slab group); the groups of one plane are
-  // consecutive on one XCD (workgroup b runs on XCD b mod 8), so its orbital
-  // rows are in that L2
-  const int i = blockIdx.x;
-  const int r = i >> 3, grp = r % NG;
-  int x, p;
-  plane_item<T, N>((r / NG) * 8 + (i & 7), npack, x, p);
-  const Pack pk = packs[p];
   const int tid = threadIdx.x;
-  for (int k = tid; k < N; k += NT) stw[k] = tw[(k % N2) * (k / N2)];
   const int64_t plane = (int64_t)x * N * N;
   const T* __restrict__ pa = phi + (int64_t)pk.a * npts + plane;
   const T* __restrict__ pb = phi + (int64_t)pk.b * npts + plane;
   const T* __restrict__ pd = phi + (int64_t)(pk.c >= 0 ? pk.d : pk.b) * npts + plane;
   const T dmask = pk.c >= 0 ? T(1) : T(0);
   cx<T> hold[Q][KH];
-  __syncthreads();
   // z step 1 over every row: tasks (y, t2), t2 fastest; the outputs of the
   // group's first slab go to LDS, those of its other slabs to registers
   // (static indices: the group is a compile-time case, the test uniform)
@@ -974,7 +969,7 @@ __global__ __launch_bounds__((slab_threads<T, N, SPW>())) void k_slab_fwd(
     __syncthreads();
     if constexpr (!ZXY) {
       // y step 2 -> global: tasks (pz, k1), pz fastest (a slab row is contiguous)
-      cx<T>* __restrict__ out = S + (int64_t)p * npts + plane + sl * ZC;
+      cx<T>* __restrict__ out = Sp + plane + sl * ZC;
       for (int task = tid; task < ZC * N1; task += NT) {
         const int pz = task % ZC, k1 = task / ZC;
         cx<T> v[N2];
@@ -997,7 +992,7 @@ __global__ __launch_bounds__((slab_threads<T, N, SPW>())) void k_slab_fwd(
         for (int t = 0; t < N2; ++t) lds[(t + N2 * k1) * PZ + pz] = v[t];
       }
       __syncthreads();
-      cx<T>* __restrict__ out = S + (int64_t)p * npts + (int64_t)x * N;
+      cx<T>* __restrict__ out = Sp + (int64_t)x * N;
       for (int e = tid; e < N * ZC; e += NT) {
         const int ky = e % N, pz = e / N;
         st_stream(&out[(int64_t)(sl * ZC + pz) * N * N + ky], lds[ky * PZ + pz]);
@@ -1019,6 +1014,33 @@ __global__ __launch_bounds__((slab_threads<T, N, SPW>())) void k_slab_fwd(
     }
     finish(grp * SPW + h);
   });
+}
+
+// On the two-slab grids, at most 128 registers: two 512-thread workgroups per CU.
+template <typename T, int N>
+constexpr int slab_fwd_waves() { return fwd_slabs<T, N>() ? 4 : 1; }
+
+template <typename T, int N, int SPW, bool ZXY>
+__global__ __launch_bounds__((slab_threads<T, N, SPW>()))
+__attribute__((amdgpu_waves_per_eu(slab_fwd_waves<T, N>()))) void k_slab_fwd(
+    const T* __restrict__ phi, const Pack* __restrict__ packs, const cx<T>* __restrict__ tw,
+    cx<T>* __restrict__ S, int npack, int64_t npts) {
+  constexpr int N2 = fft_split<N>::N2;
+  constexpr int SL = slab_count<T, N>(), PZ = N / SL + 1, NG = SL / SPW;
+  constexpr int NT = slab_threads<T, N, SPW>();
+  __shared__ cx<T> lds[N * PZ];
+  __shared__ cx<T> stw[N];
+  // item: (x, transform, slab group); the groups of one plane are
+  // consecutive on one XCD (workgroup b runs on XCD b mod 8), so its orbital
+  // rows are in that L2
+  const int i = blockIdx.x;
+  const int r = i >> 3, grp = r % NG;
+  int x, p;
+  plane_item<T, N>((r / NG) * 8 + (i & 7), npack, x, p);
+  const Pack pk = packs[p];
+  for (int k = threadIdx.x; k < N; k += NT) stw[k] = tw[(k % N2) * (k / N2)];
+  __syncthreads();
+  slab_fwd_item<T, N, SPW, ZXY, NT>(phi, pk, S + (int64_t)p * npts, x, grp, npts, lds, stw);
 }
 
 // Large-grid three-pass schedule: where a workgroup holds all slabs of a
@@ -1533,21 +1555,35 @@ __global__ void k_cast_f64_f32(const double* __restrict__ in, float* __restrict_
 // Persistent pass kernels over the whole three-pass tiles of many systems of
 // one grid size and bulk precision (a lane round: segment k of the table
 // covers items item0 .. item0 + count - 1 of one system's tile).  Forward
-// items all cost the same, so each workgroup takes every grid-th item of the
-// round, which lets it load the next item's orbitals during the current
-// one, as the single-system kernel does; middle and inverse-z/W items are
+// items (one plane of one transform) all cost the same, so each workgroup
+// takes every grid-th item of the round; middle and inverse-z/W items are
 // taken from a work queue (one atomic counter per launch) until it is empty
 // (middle items strided like the forward ones measured slower inside a
 // batch graph: 233 against 228 ms for config 4).
-// Each item runs the single-system code for its block and diagonal flag.
+// Each item runs the single-system code for its grid, block and diagonal
+// flag with the single-system thread count (the two-slab forward code on
+// these grids), so every result is bitwise the system's own build.
 // One kernel per grid size (48, 64, 80, 96: a plane fits one workgroup's
-// LDS in FP64 and FP32), with that size's 8 N threads: one kernel over all
-// sizes took the register allocation of the largest into every path, and a
-// common thread count idled threads on the smaller grids.
+// LDS in FP64 and FP32): one kernel over all sizes took the register
+// allocation of the largest into every path, and a common thread count
+// idled threads on the smaller grids.
 #define ACEX_BATCH_SIZES(X) X(48) X(64) X(80) X(96)
 
-template <int N>
-constexpr int batch_threads() { return 8 * N; }
+// Threads of a batch pass workgroup: 8 N (the single-system middle and
+// inverse-z workgroups'), or, for forward items on grids whose own forward
+// pass takes the two-slab form, that kernel's.
+template <typename T, int PASS, int N>
+constexpr int batch_threads() {
+  return PASS == 0 && fwd_slabs<T, N>() ? slab_threads<T, N, 2>() : 8 * N;
+}
+
+// LDS values of a batch pass workgroup.
+template <typename T, int PASS, int N, int B>
+constexpr int batch_lds() {
+  if constexpr (PASS == 2) return (B / 2) * zinv_rows<T, N>() * (N + 1) + N;
+  else if constexpr (PASS == 0 && fwd_slabs<T, N>()) return N * (N / 2 + 1) + N;
+  else return N * (N + 1) + N;
+}
 
 // the last segment that starts at or before item (uniform across the workgroup)
 __device__ __forceinline__ int batch_seg(const BatchSeg* __restrict__ segs, int nseg, int item) {
@@ -1584,7 +1620,7 @@ struct FwdLane {
 // Middle (PASS 1) and inverse-z/W (PASS 2, block B) items.
 template <typename T, int PASS, int N, int B>
 __device__ __forceinline__ void batch_item(const BatchSeg& g, int local, cx<T>* __restrict__ smem) {
-  constexpr int NT = batch_threads<N>();
+  constexpr int NT = batch_threads<T, PASS, N>();
   if constexpr (PASS == 1) {
     plane_mid_item<T, N, NT, true>(static_cast<cx<T>*>(g.S), static_cast<const cx<T>*>(g.tw),
                                    g.npts, T(g.g2[0]), T(g.g2[1]), T(g.g2[2]), T(g.kscale), local,
@@ -1620,14 +1656,33 @@ constexpr int batch_waves() {
 
 // PASS 0 and 1 take B = 0; PASS 2 one kernel per block.
 template <typename T, int PASS, int N, int B>
-__global__ __launch_bounds__(batch_threads<N>())
+__global__ __launch_bounds__((batch_threads<T, PASS, N>()))
 __attribute__((amdgpu_waves_per_eu(batch_waves<T, PASS, N, B>()))) void k_batch_pass(
     const BatchSeg* __restrict__ segs, int nseg, int total, int* __restrict__ counter) {
-  __shared__ cx<T> smem[PASS == 2 ? (B / 2) * zinv_rows<T, N>() * (N + 1) + N : N * (N + 1) + N];
-  if constexpr (PASS == 0) {
+  __shared__ cx<T> smem[batch_lds<T, PASS, N, B>()];
+  constexpr int NT = batch_threads<T, PASS, N>();
+  if constexpr (PASS == 0 && fwd_slabs<T, N>()) {
+    // the single-system slab kernel's items, one after another
+    constexpr int N2 = fft_split<N>::N2;
+    constexpr int64_t npts = (int64_t)N * N * N;
+    FwdLane<T, N> q{segs, nseg, total, npts};
+    cx<T>* stw = smem + N * (N / 2 + 1);
+    const cx<T>* tw = static_cast<const cx<T>*>(segs[0].tw);
+    for (int k = threadIdx.x; k < N; k += NT) stw[k] = tw[(k % N2) * (k / N2)];
+    __syncthreads();
+    for (int item = q.first(); q.more(item); item = q.next(item)) {
+      const T* phi;
+      Pack pk;
+      cx<T>* o;
+      int x;
+      q.at(item, phi, pk, o, x);
+      slab_fwd_item<T, N, 2, true, NT>(phi, pk, o, x, 0, npts, smem, stw);
+      __syncthreads();  // the item's last step read LDS
+    }
+  } else if constexpr (PASS == 0) {
     FwdLane<T, N> q{segs, nseg, total, (int64_t)N * N * N};
-    plane_fwd_loop<T, N, true, batch_threads<N>()>(q, static_cast<const cx<T>*>(segs[0].tw),
-                                                   (int64_t)N * N * N, smem, smem + N * (N + 1));
+    plane_fwd_loop<T, N, true, NT>(q, static_cast<const cx<T>*>(segs[0].tw), (int64_t)N * N * N,
+                                   smem, smem + N * (N + 1));
   } else {
     __shared__ int s_item;
     for (;;) {
@@ -1644,22 +1699,16 @@ __attribute__((amdgpu_waves_per_eu(batch_waves<T, PASS, N, B>()))) void k_batch_
   }
 }
 
-// The forward items do whole planes (the plane kernel's arithmetic): grids
-// whose own forward pass takes the two-slab form stay on their own launches,
-// so that every result is bitwise the system's own build.
 bool batch_ok(int n, int prec, int block) {
   if (block != 8 && block != 16) return false;
-  bool slabs = false;
   switch (n) {
-#define X(NN)                                                               \
-  case NN:                                                                  \
-    slabs = prec == 0 ? fwd_slabs<double, NN>() : fwd_slabs<float, NN>(); \
-    break;
+#define X(NN) case NN:
     ACEX_BATCH_SIZES(X)
 #undef X
+    break;
     default: return false;
   }
-  return !slabs && three_pass_ok(n, prec, block);
+  return three_pass_ok(n, prec, block);
 }
 
 int batch_items(int pass, int n, int npack) {
@@ -1675,7 +1724,7 @@ static int batch_per_cu() {
   if (v > 0) return v;
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_pass<T, PASS, N, B>,
-                                                   batch_threads<N>(), 0) != hipSuccess ||
+                                                   batch_threads<T, PASS, N>(), 0) != hipSuccess ||
       occ < 1)
     occ = 1;
   cached.store(occ, std::memory_order_relaxed);
@@ -1685,13 +1734,14 @@ static int batch_per_cu() {
 template <typename T, int PASS, int N, int B>
 static hipError_t batch_launch(const BatchSeg* segs, int nseg, int total, int* counter, int cus,
                                hipStream_t s) {
-  static_assert(zinv_threads<T, N>() <= batch_threads<N>(), "a thread per inverse-z point");
+  static_assert(PASS != 2 || zinv_threads<T, N>() <= batch_threads<T, PASS, N>(),
+                "a thread per inverse-z point");
   static_assert(plane_ok<T, N>(), "a plane per workgroup");
   // persistent, the whole chip (one workgroup per item measured slower,
   // 246-255 against 228 ms for config 4, and so did half or a quarter of
   // the chip per launch, 249 and 383 ms)
   const int grid = std::min(total, cus * batch_per_cu<T, PASS, N, B>());
-  hipLaunchKernelGGL((k_batch_pass<T, PASS, N, B>), dim3(grid), dim3(batch_threads<N>()), 0, s,
+  hipLaunchKernelGGL((k_batch_pass<T, PASS, N, B>), dim3(grid), dim3(batch_threads<T, PASS, N>()), 0, s,
                      segs, nseg, total, counter);
   return hipGetLastError();
 }

@@ -19,10 +19,13 @@ TOL = 1e-10
 
 # (n, orbitals, precision, (block, chunk, pencils), mask: None, "random" or
 # "tail" (pairs of the first 16 orbitals all kept, the rest random))
-# The last five take the persistent batch passes for their whole tiles: a
-# lane of two instances with unequal tile counts (48 FP32), one instance with
-# a mask whose leading tiles are complete, and the partial tiles of all of
-# them between the passes.
+# From the sixth on they take the persistent batch passes for their whole
+# tiles: a lane of two instances with unequal tile counts (48 FP32), one
+# instance with a mask whose leading tiles are complete, and the partial
+# tiles of all of them between the passes.  The last five complete the
+# grid sizes and precisions of the lanes: there the system's own forward
+# pass takes each plane as two slabs and the lane's items whole planes, with
+# the same operations per element, so the bits must agree.
 INSTANCES = [
     (16, 4, "fp64", (16, 0, 0), None),
     (24, 13, "fp64", (8, 0, 8), None),
@@ -34,6 +37,11 @@ INSTANCES = [
     (48, 9, "fp32", (8, 0, 0), None),
     (64, 22, "fp64", (8, 0, 0), "tail"),
     (80, 8, "fp32", (8, 0, 16), None),
+    (48, 8, "fp64", (8, 0, 0), None),
+    (64, 8, "fp32", (8, 0, 0), None),
+    (80, 8, "fp64", (8, 0, 0), None),
+    (96, 8, "fp64", (8, 0, 0), None),
+    (96, 8, "fp32", (8, 0, 0), None),
 ]
 
 
@@ -111,15 +119,16 @@ def _assert_same(out, refs):
 
 def test_batch_graph_matches_separate_builds_and_replays(lib, systems):
     import torch
-    _say("batch graph: %d uneven instances n=16..80" % len(systems))
+    _say("batch graph: %d uneven instances n=16..96" % len(systems))
     plans = _plans(lib, systems)
     phis = [_dev(s.phi) for _, s, _, _, _ in systems]
     refs = _separate(lib, plans, systems, phis)
     batch = lib.Batch(plans, [m for *_, m in systems])
     # lanes: 48^3 FP32 block 8 (two instances), 64^3 FP64 block 16 and
-    # block 8 (one each), 80^3 FP32 block 8 (one)
+    # block 8 (one each), 80^3 FP32 block 8 (one), and one each of 48^3
+    # FP64, 64^3 FP32, 80^3 FP64, 96^3 FP64 and FP32, block 8
     lanes, whole, other = batch.lanes()
-    assert lanes == 4 and whole > 0 and other > 0
+    assert lanes == 9 and whole > 0 and other > 0
     ws = lib.workspace(batch.workspace_bytes())
     out = batch.outputs(phis)
     batch.build_into(phis, out, ws)
