@@ -1052,21 +1052,22 @@ __attribute__((amdgpu_waves_per_eu(slab_fwd_waves<T, N>()))) void k_slab_fwd(
 // values and the plane leaves in natural y, in place.  The inverse z and W
 // pass is then the plane-fitting grids' one.
 
-template <typename T, int N>
-__global__ __launch_bounds__((slab_threads<T, N, slab_count<T, N>()>())) void
-k_slab_mid(cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts, T g0,
-           T g1, T g2, T kscale) {
+// The work of one slab middle-pass workgroup of NT threads: item bid = (kz
+// position, transform); lds holds N (ZC + 1) values, stw the N four-step
+// twiddles, filled before the call (the first slab starts with a barrier).
+// The slab kernel runs one item per workgroup; the batch middle items on
+// the grids that take this form run the same function with the same
+// thread count, so their results are bitwise the same.
+template <typename T, int N, int NT>
+__device__ __forceinline__ void slab_mid_item(cx<T>* __restrict__ S, int64_t npts, T g0, T g1,
+                                              T g2, T kscale, int bid, cx<T>* __restrict__ lds,
+                                              const cx<T>* __restrict__ stw) {
   constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2;
   constexpr int SL = slab_count<T, N>(), ZC = N / SL, K1S = ZC / N2, PZ = ZC + 1;
-  constexpr int NT = slab_threads<T, N, SL>();
   constexpr int Q = (N * N2 + NT - 1) / NT;   // final-step tasks (x, t2) per thread
   constexpr int KH = (SL - 1) * K1S;          // values held per task
-  __shared__ cx<T> lds[N * PZ];
-  __shared__ cx<T> stw[N];
-  const int bid = blockIdx.x;
   const int pz = bid % N, p = bid / N;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];
   cx<T>* __restrict__ io = S + (int64_t)p * npts + (int64_t)pz * N * N;
   const int kz = freq_of_pos<N>(pz);
   cx<T> hold[Q][KH];
@@ -1156,6 +1157,32 @@ k_slab_mid(cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64
       }
     }
   });
+}
+
+// Plane-fitting grids whose plane workgroup takes more than half of a CU's
+// LDS (FP64 80^3 and 96^3, FP32 120^3 and 128^3) run the middle pass slab by
+// slab too: 512 threads and half a plane of LDS, two workgroups per CU.
+// One 128-transform launch, slabs against planes: FP64 96^3 714 / 750 us,
+// 80^3 409 / 483; FP32 128^3 838 / 1011, 120^3 810 / 1018 (FP32 96^3, whose
+// plane workgroups already fit twice, 397 / 371).
+template <typename T, int N>
+constexpr bool mid_slabs() {
+  return plane_ok<T, N>() && slab_count<T, N>() == 2 &&
+         2 * (((long)N * (N + 1) + N) * (long)sizeof(cx<T>) + 64) > kLdsBytes;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((slab_threads<T, N, slab_count<T, N>()>()))
+__attribute__((amdgpu_waves_per_eu(mid_slabs<T, N>() ? 4 : 1))) void
+k_slab_mid(cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts, T g0,
+           T g1, T g2, T kscale) {
+  constexpr int N2 = fft_split<N>::N2;
+  constexpr int SL = slab_count<T, N>(), PZ = N / SL + 1;
+  constexpr int NT = slab_threads<T, N, SL>();
+  __shared__ cx<T> lds[N * PZ];
+  __shared__ cx<T> stw[N];
+  for (int i = threadIdx.x; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];
+  slab_mid_item<T, N, NT>(S, npts, g0, g1, g2, kscale, blockIdx.x, lds, stw);
 }
 
 // ------------------------------------------------------------------ z rows (fallback)
@@ -1574,14 +1601,17 @@ __global__ void k_cast_f64_f32(const double* __restrict__ in, float* __restrict_
 // pass takes the two-slab form, that kernel's.
 template <typename T, int PASS, int N>
 constexpr int batch_threads() {
-  return PASS == 0 && fwd_slabs<T, N>() ? slab_threads<T, N, 2>() : 8 * N;
+  return (PASS == 0 && fwd_slabs<T, N>()) || (PASS == 1 && mid_slabs<T, N>())
+             ? slab_threads<T, N, 2>()
+             : 8 * N;
 }
 
 // LDS values of a batch pass workgroup.
 template <typename T, int PASS, int N, int B>
 constexpr int batch_lds() {
   if constexpr (PASS == 2) return (B / 2) * zinv_rows<T, N>() * (N + 1) + N;
-  else if constexpr (PASS == 0 && fwd_slabs<T, N>()) return N * (N / 2 + 1) + N;
+  else if constexpr ((PASS == 0 && fwd_slabs<T, N>()) || (PASS == 1 && mid_slabs<T, N>()))
+    return N * (N / 2 + 1) + N;
   else return N * (N + 1) + N;
 }
 
@@ -1621,7 +1651,11 @@ struct FwdLane {
 template <typename T, int PASS, int N, int B>
 __device__ __forceinline__ void batch_item(const BatchSeg& g, int local, cx<T>* __restrict__ smem) {
   constexpr int NT = batch_threads<T, PASS, N>();
-  if constexpr (PASS == 1) {
+  if constexpr (PASS == 1 && mid_slabs<T, N>()) {
+    // twiddles filled once per launch (the same for every segment)
+    slab_mid_item<T, N, NT>(static_cast<cx<T>*>(g.S), g.npts, T(g.g2[0]), T(g.g2[1]),
+                            T(g.g2[2]), T(g.kscale), local, smem, smem + N * (N / 2 + 1));
+  } else if constexpr (PASS == 1) {
     plane_mid_item<T, N, NT, true>(static_cast<cx<T>*>(g.S), static_cast<const cx<T>*>(g.tw),
                                    g.npts, T(g.g2[0]), T(g.g2[1]), T(g.g2[2]), T(g.kscale), local,
                                    smem, smem + N * (N + 1));
@@ -1685,6 +1719,12 @@ __attribute__((amdgpu_waves_per_eu(batch_waves<T, PASS, N, B>()))) void k_batch_
                                    smem, smem + N * (N + 1));
   } else {
     __shared__ int s_item;
+    if constexpr (PASS == 1 && mid_slabs<T, N>()) {
+      constexpr int N2 = fft_split<N>::N2;
+      cx<T>* stw = smem + N * (N / 2 + 1);
+      const cx<T>* tw = static_cast<const cx<T>*>(segs[0].tw);
+      for (int k = threadIdx.x; k < N; k += NT) stw[k] = tw[(k % N2) * (k / N2)];
+    }
     for (;;) {
       if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
       __syncthreads();
@@ -1908,7 +1948,13 @@ static hipError_t inv_yz_t(const GridArgs& g, void* S, int npack, hipStream_t s)
 
 template <typename T, int N>
 static hipError_t mid_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
-  if constexpr (plane_ok<T, N>()) {
+  if constexpr (mid_slabs<T, N>()) {
+    constexpr int SL = slab_count<T, N>();
+    hipLaunchKernelGGL((k_slab_mid<T, N>), dim3(N * npack), dim3(slab_threads<T, N, SL>()), 0,
+                       s, static_cast<cx<T>*>(S), static_cast<const cx<T>*>(g.tw), npack, g.npts,
+                       T(g.g2[0]), T(g.g2[1]), T(g.g2[2]), T(g.kscale));
+    return hipGetLastError();
+  } else if constexpr (plane_ok<T, N>()) {
     hipLaunchKernelGGL((k_plane_mid<T, N>), dim3(N * npack), dim3(plane_threads<N>()), 0, s,
                        static_cast<cx<T>*>(S), static_cast<const cx<T>*>(g.tw), npack, g.npts,
                        T(g.g2[0]), T(g.g2[1]), T(g.g2[2]), T(g.kscale));
