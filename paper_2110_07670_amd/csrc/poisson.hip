@@ -576,8 +576,8 @@ constexpr bool slab3_ok() {
   return slab_ok<T, N>() && slab_spw<T, N>() == slab_count<T, N>();
 }
 
-// Plane-fitting grids from 48^3 up also run the three-pass forward pass as
-// two slabs: one 512-thread workgroup per plane takes both slabs from one
+// Plane-fitting grids from 48^3 up also run the forward pass as two slabs
+// (both layouts): one 512-thread workgroup per plane takes both slabs from one
 // first step, holding the second slab's first-step outputs in registers;
 // half a plane of LDS lets two or more such workgroups share a CU, so that
 // one's transform steps overlap another's loads and stores.  (A plane
@@ -589,7 +589,9 @@ constexpr bool slab3_ok() {
 // kernel's earlier FP32 prefetch placement), 96^3 300 / 341, 80^3 122 / 198,
 // 64^3 62 / 65, 48^3 52 / 57.  Per build, the forward pass of the 96^3 FP64
 // build of 128 orbitals 17.4 -> 16.1 ms, of the 128^3 FP32 build of 256
-// orbitals 105 -> 101 ms.
+// orbitals 105 -> 101 ms.  In the four-pass layout S[x][ky][kz]: FP64 96^3
+// 510 / 668 us, 64^3 100 / 184; FP32 128^3 657 / 804, 96^3 271 / 352, 48^3
+// 49 / 58.
 template <typename T, int N>
 constexpr bool fwd_slabs() {
   return plane_ok<T, N>() && N >= 48 && slab_count<T, N>() == 2;
@@ -1883,12 +1885,15 @@ static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs
                            void* S, bool zxy, hipStream_t s) {
   const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
   if constexpr (fwd_slabs<T, N>()) {
-    if (zxy) {
+    if (zxy)
       hipLaunchKernelGGL((k_slab_fwd<T, N, 2, true>), dim3(N * npack),
                          dim3(slab_threads<T, N, 2>()), 0, s, static_cast<const T*>(phi), packs,
                          tw, static_cast<cx<T>*>(S), npack, g.npts);
-      return hipGetLastError();
-    }
+    else
+      hipLaunchKernelGGL((k_slab_fwd<T, N, 2, false>), dim3(N * npack),
+                         dim3(slab_threads<T, N, 2>()), 0, s, static_cast<const T*>(phi), packs,
+                         tw, static_cast<cx<T>*>(S), npack, g.npts);
+    return hipGetLastError();
   }
   if constexpr (plane_ok<T, N>()) {
     const int items = N * npack;
