@@ -270,8 +270,9 @@ int ace_plan_set_schedule(ace_plan *plan, int schedule);
  * inverse z with W), ACE_TILES_ROWS_FUSED (forward, x, inverse y, inverse z
  * rows with W) or ACE_TILES_FOUR_PASS (forward, x, inverse y/z, W), the
  * schedule of full tiles; other tiles take four passes.  *plane is 1 where
- * a (y, z) plane fits LDS and 0 where the forward pass works slab by slab
- * and a four-pass inverse y/z is a line pass plus a row pass. */
+ * a (y, z) plane fits LDS (a four-pass inverse y/z is one plane pass) and 0
+ * where it does not (a four-pass inverse y/z is a line pass plus a row
+ * pass); the forward pass moves the same bytes in either case. */
 #define ACE_TILES_THREE_PASS 0
 #define ACE_TILES_ROWS_FUSED 1
 #define ACE_TILES_FOUR_PASS 2
