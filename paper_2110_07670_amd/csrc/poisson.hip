@@ -414,6 +414,99 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_inv(
   }
 }
 
+// The same inverse, a slab of kz positions at a time: per slab the inverse
+// y transform of its ZC columns and the in-slab inverse z step; each thread
+// keeps its share of the first slab's z-step outputs in registers, and after
+// the second slab the first inverse z step runs on the held values and the
+// plane leaves in natural order, in place (every slab has been read by
+// then).  Half a plane of LDS and 512 threads, so that two workgroups share
+// a CU; the same values, bit for bit, as the plane kernel (inv_slabs says
+// where it is used).
+template <typename T, int N>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_slab_inv(
+    cx<T>* __restrict__ S, const cx<T>* __restrict__ tw, int npack, int64_t npts) {
+  constexpr int N1 = fft_split<N>::N1, N2 = fft_split<N>::N2;
+  constexpr int SL = 2, ZC = N / SL, K1S = ZC / N2, PZ = ZC + 1;
+  constexpr int NT = 512;
+  constexpr int Q = (N * N2 + NT - 1) / NT;  // final-step tasks (y, t2) per thread
+  static_assert(N % SL == 0 && ZC % N2 == 0, "whole second-step blocks per slab");
+  __shared__ cx<T> lds[N * PZ];
+  __shared__ cx<T> stw[N];
+  const int bid = blockIdx.x;
+  const int x = bid % N, p = bid / N;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) stw[i] = tw[(i % N2) * (i / N2)];
+  cx<T>* __restrict__ io = S + (int64_t)p * npts + (int64_t)x * N * N;
+  cx<T> hold[Q][K1S];
+  sfor<0, SL>([&](auto sc) {
+    constexpr int sl = decltype(sc)::value;
+    __syncthreads();  // twiddles in place / the previous slab read out of LDS
+    // y step 2 inverse: the slab's columns -> LDS, tasks (pz, k1), pz fastest
+    for (int task = tid; task < ZC * N1; task += NT) {
+      const int pz = task % ZC, k1 = task / ZC;
+      cx<T> v[N2];
+#pragma unroll
+      for (int t = 0; t < N2; ++t) v[t] = io[(int64_t)(t + N2 * k1) * N + sl * ZC + pz];
+      dft<N2, true>(v);
+#pragma unroll
+      for (int t = 0; t < N2; ++t) lds[(t + N2 * k1) * PZ + pz] = v[t];
+    }
+    __syncthreads();
+    // y step 1 inverse to natural y: tasks (pz, t2), pz fastest
+    for (int task = tid; task < ZC * N2; task += NT) {
+      const int pz = task % ZC, t2 = task / ZC;
+      cx<T> v[N1];
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmulc(lds[(t2 + N2 * k1) * PZ + pz], stw[k1 * N2 + t2]);
+      dft<N1, true>(v);
+#pragma unroll
+      for (int j1 = 0; j1 < N1; ++j1) lds[(t2 + N2 * j1) * PZ + pz] = v[j1];
+    }
+    __syncthreads();
+    // z step 2 inverse within the slab's blocks: tasks (y, k), y fastest
+    for (int task = tid; task < N * K1S; task += NT) {
+      const int y = task % N, k = task / N;
+      cx<T> v[N2];
+#pragma unroll
+      for (int t = 0; t < N2; ++t) v[t] = lds[y * PZ + t + N2 * k];
+      dft<N2, true>(v);
+#pragma unroll
+      for (int t = 0; t < N2; ++t) lds[y * PZ + t + N2 * k] = v[t];
+    }
+    __syncthreads();
+    if constexpr (sl == 0) {
+      // this thread's tasks (y, t2), t2 fastest: the slab's K1S values
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int task = tid + q * NT;
+        if (task < N * N2) {
+          const int t2 = task % N2, y = task / N2;
+#pragma unroll
+          for (int k = 0; k < K1S; ++k) hold[q][k] = lds[y * PZ + t2 + N2 * k];
+        }
+      }
+    } else {
+      // z step 1 inverse -> global, natural order: tasks (y, t2)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int task = tid + q * NT;
+        if (task < N * N2) {
+          const int t2 = task % N2, y = task / N2;
+          cx<T> v[N1];
+#pragma unroll
+          for (int k1 = 0; k1 < N1; ++k1) {
+            const cx<T> u = k1 < K1S ? hold[q][k1 < K1S ? k1 : 0] : lds[y * PZ + t2 + N2 * (k1 - K1S)];
+            v[k1] = cmulc(u, stw[k1 * N2 + t2]);
+          }
+          dft<N1, true>(v);
+#pragma unroll
+          for (int j1 = 0; j1 < N1; ++j1) io[(int64_t)y * N + t2 + N2 * j1] = v[j1];
+        }
+      }
+    }
+  });
+}
+
 // Full, unmasked tile: the schedule packs the pairs of each row a two per
 // transform, (a, b) and (a, b + 1), with a row's odd leftover alone, so the
 // pair -> (transform, half) map is known at compile time and each transform
@@ -1934,10 +2027,20 @@ static hipError_t fwd_yz_t(const GridArgs& g, const void* phi, const Pack* packs
   return hipGetLastError();
 }
 
+// The slab inverse on the FP32 grids whose plane takes more than half of
+// LDS: one 128-transform launch at 128^3 808 against 1016 us; at FP64 96^3
+// and 80^3 the plane kernel already moves 5.2 TB/s and the slab form is no
+// faster (713 / 695 us, 406 / 405), at FP32 96^3 slower (354 / 333).
+template <typename T, int N>
+constexpr bool inv_slabs() { return sizeof(T) == 4 && mid_slabs<T, N>(); }
+
 template <typename T, int N>
 static hipError_t inv_yz_t(const GridArgs& g, void* S, int npack, hipStream_t s) {
   const cx<T>* tw = static_cast<const cx<T>*>(g.tw);
-  if constexpr (plane_ok<T, N>()) {
+  if constexpr (inv_slabs<T, N>()) {
+    hipLaunchKernelGGL((k_slab_inv<T, N>), dim3(N * npack), dim3(512), 0, s,
+                       static_cast<cx<T>*>(S), tw, npack, g.npts);
+  } else if constexpr (plane_ok<T, N>()) {
     hipLaunchKernelGGL((k_plane_inv<T, N>), dim3(N * npack), dim3(plane_threads<N>()), 0, s,
                        static_cast<cx<T>*>(S), tw, npack, g.npts);
   } else {

@@ -29,7 +29,7 @@ KERNEL_SOURCE = os.path.join(HERE, "csrc", "poisson.hip")
 
 STAGE_OF = [
     ("k_plane_fwd", "yz_fwd"), ("k_rows_fwd", "yz_fwd"), ("k_slab_fwd", "yz_fwd"),
-    ("k_slab_mid", "x_poisson"), ("k_plane_inv", "yz_inv"),
+    ("k_slab_mid", "x_poisson"), ("k_plane_inv", "yz_inv"), ("k_slab_inv", "yz_inv"),
     ("k_rows_inv", "yz_inv"), ("k_accumulate", "w_accumulate"), ("k_zinv_acc", "w_accumulate"),
     ("k_plane_mid", "x_poisson"), ("k_gemm_abt", "abt_product"),
     ("k_reduce_splits", "abt_product"), ("k_gemm_ab", "ab_product"), ("k_chol_left", "cholesky_inv"),
