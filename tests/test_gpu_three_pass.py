@@ -89,10 +89,11 @@ def test_three_pass_repeatable(lib):
     assert np.array_equal(a["W"], b["W"]) and np.array_equal(a["xi"], b["xi"])
 
 
-@pytest.mark.parametrize("n", [96, 128, 160])
+@pytest.mark.parametrize("n", [96, 120, 128, 160])
 def test_three_pass_fp32_matches_four_pass(lib, n):
     """FP32 bulk, block 16: the two schedules agree to FP32 rounding; both
-    stay within the FP32 bound against the FP64 build (at 160^3 the automatic
+    stay within the FP32 bound against the FP64 build (at 120^3 and 128^3 the
+    four-pass inverse y/z works slab by slab; at 160^3 the automatic
     schedule is the large-grid one: slab forward pass, row-form inverse z)."""
     _say("three-pass fp32 n=%d orbitals 32" % n)
     spec = synth.SystemSpec("t3f", 0.11 * n + 5.0, n, 32, "random", 0, (1.0, 1.4), 0.25, 500 + n)
